@@ -1,0 +1,163 @@
+/*
+ * lbm.h -- C ABI of the MI355X library for the multiphase lattice Boltzmann
+ * model with self-tuning equation of state of Huang, Wu & Adams
+ * (arXiv:1809.02390): the D2Q9 step with the pairwise interaction force
+ * (main Eq. 12), the moment-space collision with built-in EOS, velocity-
+ * dependent collision matrix, cubic-velocity corrections and the epsilon^3
+ * consistency term (main Eq. 13 = supplement Eq. 1, executed by the
+ * six-step sequence of supplement Sec. IV), and streaming (supplement Eq. 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Lattice units: dx = dt = c = 1, c_s^2 = 1/3.  Periodic in x and y.
+ *  - Fields are row-major with x fastest: element (y, x) of an ny-by-nx
+ *    field sits at offset y*nx + x.  Distribution arrays are structure-of-
+ *    arrays, population i (velocity order of supplement Eq. 3: rest, +x, +y,
+ *    -x, -y, +x+y, -x+y, -x-y, +x-y) at offset i*nx*ny.
+ *  - Pointers named f_*, rho*, u*, lam*, drho* are DEVICE pointers owned by
+ *    the caller (any allocator; the library never frees them).  Pointers
+ *    named *_out, totals, dtheta, out are HOST pointers.
+ *  - Every call is asynchronous on the stream given to lbm_create (or
+ *    lbm_set_stream), except where stated: lbm_init and lbm_moments
+ *    synchronise that stream to return host results.
+ *  - Every int-returning call returns LBM_OK (0) or a negative status;
+ *    lbm_last_error() then returns a message for the calling thread.  A
+ *    failed call launches nothing and leaves the state unchanged, except
+ *    LBM_EHIP (a HIP runtime error), after which the state is undefined.
+ *  - The library allocates only small device scratch inside the context
+ *    (reduction partials and a status word); lbm_destroy frees it.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx; /* opaque, library-owned host object */
+
+enum lbm_status {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,     /* invalid argument or parameter                   */
+  LBM_ENOCOEX = -2,    /* no two-phase coexistence (Maxwell solve failed)  */
+  LBM_EHIP = -3,       /* HIP runtime error                                */
+  LBM_ENONFINITE = -4, /* a non-finite total mass or momentum was found    */
+  LBM_ESTATE = -5      /* call not valid in the current state              */
+};
+
+enum lbm_storage {
+  LBM_FP32 = 0, /* f_i stored as float                                   */
+  LBM_FP16 = 1, /* f_i stored as binary16 scaled deviations (see create)  */
+  LBM_BF16 = 2  /* f_i stored as bfloat16 scaled deviations               */
+};
+
+/* The paper's problem statement: lattice, relaxation rates, varpi, the
+ * Carnahan-Starling EOS parameters (main Eq. 20), and the prescribed surface
+ * tension and interface thickness (main Eq. 23). */
+typedef struct lbm_params {
+  int32_t nx, ny;  /* lattice size, >= 1 each, nx*ny*9 < 2^31            */
+  int32_t storage; /* enum lbm_storage                                   */
+  int32_t reserved;/* must be 0                                          */
+  double s_p;      /* shear rate, 0 < s_p < 2; nu = (1/s_p - 1/2)/3      */
+  double s_eps;    /* rate of the energy-square moment; <= 0 means s_e   */
+  double varpi;    /* bulk-viscosity coefficient, 0 < varpi < 1, != 1/3  */
+  double a, b;     /* CS attraction and co-volume, > 0                   */
+  double r_gas;    /* gas constant R, > 0                                */
+  double tr;       /* reduced temperature T/T_c, 0 < tr < 1              */
+  double sigma;    /* surface tension (lattice units); <= 0 means the
+                      paper's sound-speed rule, lbm_sigma_paper()        */
+  double width;    /* 5%-95% interface thickness W (lattice units), > 0  */
+} lbm_params;
+
+/* Coefficients the parameter map derives (all FP64, lattice units). */
+typedef struct lbm_derived {
+  double rho_g, rho_l, p0;   /* Maxwell coexistence densities and pressure  */
+  double c_sigma, c_w;       /* flat-interface sigma and W at K_EOS=K_INT=1 */
+  double sigma, width;       /* the prescribed (or default) sigma, W        */
+  double k_int, k_eos;       /* K_INT = W/C_W, K_EOS = sigma/(C_sigma K_INT) */
+  double g2;                 /* G^2 = 2 K_INT^2 K_EOS a (main Eq. 21)       */
+  double kp;                 /* K' = K_EOS, prefactor of the CS pressure    */
+  double rt;                 /* R T = R tr T_c                              */
+  double alpha2, beta2;      /* main Eq. 7 with alpha1 = -1, beta1 = 1      */
+  double k, h, bs;           /* k, h, b of main Eq. 7                       */
+  double s_p, s_q, s_e, s_eps; /* rates; s_q, s_e from main Eq. 16         */
+  double tc;                 /* critical temperature of the CS constants    */
+} lbm_derived;
+
+/* Message for the last failed call on this thread ("" if none). */
+const char* lbm_last_error(void);
+
+/* Host-only parameter map (no GPU needed).  Validates *p and fills *out:
+ * Maxwell construction (main Eq. 19), C_sigma and C_W from the flat
+ * interface of the pressure tensor (main Eqs. 17-18), the sigma/W map
+ * (main Eqs. 21, 23), coefficients (main Eq. 7) and rates (main Eq. 16).
+ * Returns LBM_EINVAL for bad parameters, LBM_ENOCOEX if the Maxwell solve
+ * fails. */
+int lbm_derive(const lbm_params* p, lbm_derived* out);
+
+/* Host-only: the sigma at which the paper's sound-speed rule (main Eq. 22)
+ * gives lattice speed c = 1 for thickness `width` at `tr`. */
+int lbm_sigma_paper(double width, double tr, double a, double b, double r_gas,
+                    double* sigma_out);
+
+/* Bytes of ONE distribution buffer (the caller provides two, A and B):
+ * 9*nx*ny*4 for LBM_FP32, 9*nx*ny*2 for the 2-byte storages.  0 on error. */
+size_t lbm_state_bytes(const lbm_params* p);
+
+/* Bytes of the reference-density buffer the 2-byte storages need (two
+ * binary16 planes of nx*ny); 0 for LBM_FP32 or on error. */
+size_t lbm_ref_bytes(const lbm_params* p);
+
+/* Create a context over caller-owned device buffers f_a, f_b (each
+ * lbm_state_bytes) and rho_ref (lbm_ref_bytes; may be NULL for LBM_FP32),
+ * on HIP stream `stream` (a hipStream_t; NULL = default stream), on the
+ * current HIP device.  Derives the coefficients; launches nothing.  The
+ * state is uninitialised until lbm_init or lbm_set_state. */
+int lbm_create(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b,
+               void* rho_ref, void* stream);
+
+/* Change the stream used by later calls. */
+int lbm_set_stream(lbm_ctx* ctx, void* stream);
+
+/* Initial state f_i = (M^-1 m^eq(rho0, u0, eta(rho0)))_i at t = 0 (main
+ * Eq. 3; zero velocity when ux0 / uy0 are NULL).  rho0, ux0, uy0 are device
+ * float fields of nx*ny.  Synchronises the stream; LBM_EINVAL if any rho0 is
+ * not finite, <= 0 or >= 4/b (the pole of the CS EOS). */
+int lbm_init(lbm_ctx* ctx, const float* rho0, const float* ux0, const float* uy0);
+
+/* Load a post-streaming state f(t) (device float, 9*nx*ny, layout above)
+ * and set the step counter to 0. */
+int lbm_set_state(lbm_ctx* ctx, const float* f);
+
+/* Export the post-streaming state f(t) as device float (9*nx*ny). */
+int lbm_get_state(lbm_ctx* ctx, float* f);
+
+/* Advance n >= 0 time steps; each step is one fused kernel launch
+ * (density halo, force, collision, streaming) alternating A and B. */
+int lbm_step(lbm_ctx* ctx, int32_t n);
+
+/* Macroscopic fields at the current time: rho = sum_i f_i and
+ * u = (sum_i e_i f_i + F/2)/rho (main Eq. 5), written to the device float
+ * fields rho, ux, uy (each may be NULL), and, if totals is not NULL, the
+ * FP64 totals {sum rho, sum_x sum_i e_ix f_i, sum_x sum_i e_iy f_i} reduced
+ * deterministically on the device (synchronises the stream).  Returns
+ * LBM_ENONFINITE if a total is not finite. */
+int lbm_moments(lbm_ctx* ctx, float* rho, float* ux, float* uy, double totals[3]);
+
+/* Number of steps taken since lbm_init / lbm_set_state. */
+int64_t lbm_time(const lbm_ctx* ctx);
+
+/* Copy the derived coefficients of a context. */
+int lbm_get_derived(const lbm_ctx* ctx, lbm_derived* out);
+
+/* Destroy a context (frees its scratch; never the caller's buffers). */
+void lbm_destroy(lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,256 @@
+// Per-node arithmetic of the self-tuning-EOS D2Q9 model, shared by every
+// kernel of the library.  All functions are __host__ __device__ templates on
+// the real type; the kernels instantiate them with float.
+//
+// Moment order (supplement Eq. 4): rho, e, eps, j_x, q_x, j_y, q_y, p_xx,
+// p_xy.  Velocity order (supplement Eq. 3): rest, +x, +y, -x, -y, +x+y,
+// -x+y, -x-y, +x-y.  Lattice units dx = dt = c = 1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace lbm {
+
+// Scalars of one collision, precomputed on the host (FP64 -> T).
+template <typename T>
+struct Coef {
+  T g2;        // G'^2 (force strength, main Eq. 12)
+  T kp, rt;    // K' = K_EOS and R T of the CS pressure (main Eq. 20)
+  T a, b4;     // a and b/4
+  T alpha2, beta2;
+  // step (2) of supplement Sec. IV
+  T k_seps_h;  // k s_eps / 2
+  T h_sq_h;    // h s_q / 2
+  T b_sq;      // b s_q
+  T b_sq_h;    // b s_q / 2
+  // step (3): 1 - s/2
+  T om_e, om_eps, om_q, om_p;
+  // step (4): nonzero entries of R, T, X (supplement Eqs. 34, 37, 40)
+  T cR11, cR17, cR18, cT1, one_mk, twok_h, cX1;
+  T cR71, cR77, cT7, two_b, cX7;
+  T cR81, cR88, cT8, cX8;
+  // step (6)
+  T s_e, kq2, s_eps, s_p;  // kq2 = k (s_e/2 - 1) s_eps
+};
+
+// rho = sum_i f_i accumulated in FP64: for nine populations of one node the
+// double sum is exact, so every density (tile, ring, collision) is the same
+// correctly rounded value of the exact mass of the node.
+template <typename T>
+__host__ __device__ __forceinline__ double density_exact(const T* f) {
+  double s = (double)f[0];
+#pragma unroll
+  for (int i = 1; i < 9; ++i) s += (double)f[i];
+  return s;
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ T density(const T* f) {
+  return (T)density_exact(f);
+}
+
+// Stencil of main Eq. 12 (the weights 1/3 and 1/12, unit spacing):
+// g = sum_i w_i rho(x + e_i) e_i.  Arguments are the eight neighbour
+// densities named by direction.
+template <typename T>
+__host__ __device__ __forceinline__ void stencil(T rE, T rN, T rW, T rS, T rNE, T rNW, T rSW, T rSE, T& gx,
+                                                 T& gy) {
+  const T third = T(1) / T(3), twelfth = T(1) / T(12);
+  const T dd1 = rNE - rSW, dd2 = rSE - rNW;  // the two diagonals
+  gx = third * (rE - rW) + twelfth * (dd1 + dd2);
+  gy = third * (rN - rS) + twelfth * (dd1 - dd2);
+}
+
+// Pressure of the lattice Boltzmann equation and its density slope:
+// p_LBE = K'[rho R T Z - a rho^2] + G^2 rho^2/2 (main Eqs. 18, 20),
+// Z = (1 + v + v^2 - v^3)/(1 - v)^3, d(rho Z)/d rho = (1 + 4v + 4v^2 - 4v^3 + v^4)/(1 - v)^4.
+template <typename T>
+__host__ __device__ __forceinline__ void eos(T rho, const Coef<T>& c, T& p_lbe, T& dp_lbe) {
+  const T v = c.b4 * rho;
+  const T iw = T(1) / (T(1) - v);
+  const T iw3 = iw * iw * iw;
+  const T z = (T(1) + v * (T(1) + v * (T(1) - v))) * iw3;
+  const T dz = (T(1) + v * (T(4) + v * (T(4) + v * (v - T(4))))) * (iw3 * iw);
+  p_lbe = c.kp * rho * (c.rt * z - c.a * rho) + T(0.5) * c.g2 * rho * rho;
+  dp_lbe = c.kp * (c.rt * dz - T(2) * c.a * rho) + c.g2 * rho;
+}
+
+// m = M f (supplement Eq. 4) as an add/subtract tree; m[0] is density(f).
+template <typename T>
+__host__ __device__ __forceinline__ void forward_moments(const T* f, T* m) {
+  const T a13 = f[1] + f[3], a24 = f[2] + f[4], d57 = f[5] + f[7], d68 = f[6] + f[8];
+  const T s13 = f[1] - f[3], s24 = f[2] - f[4], e57 = f[5] - f[7], e86 = f[8] - f[6];
+  const T ax = a13 + a24, dg = d57 + d68;
+  m[0] = density(f);
+  m[1] = T(2) * dg - ax - T(4) * f[0];
+  m[2] = T(4) * f[0] - T(2) * ax + dg;
+  m[3] = s13 + (e57 + e86);
+  m[4] = (e57 + e86) - T(2) * s13;
+  m[5] = s24 + (e57 - e86);
+  m[6] = (e57 - e86) - T(2) * s24;
+  m[7] = a13 - a24;
+  m[8] = d57 - d68;
+}
+
+// f = M^-1 m = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m.
+// The rest population is formed last as the exact mass `mass` minus the
+// eight moving populations (FP64, exact), so the only change of the node's
+// mass is the one unbiased rounding of f_0; with the rounding of 1/9 it
+// would drift systematically.
+template <typename T>
+__host__ __device__ __forceinline__ void inverse_moments(const T* m, T* f, double mass) {
+  const T w0 = m[0] * T(1.0 / 9.0), w1 = m[1] * T(1.0 / 36.0), w2 = m[2] * T(1.0 / 36.0);
+  const T w3 = m[3] * T(1.0 / 6.0), w4 = m[4] * T(1.0 / 12.0);
+  const T w5 = m[5] * T(1.0 / 6.0), w6 = m[6] * T(1.0 / 12.0);
+  const T w7 = m[7] * T(0.25), w8 = m[8] * T(0.25);
+  const T A = w0 - w1 - T(2) * w2, X = w3 - T(2) * w4, Y = w5 - T(2) * w6;
+  f[1] = (A + w7) + X;
+  f[3] = (A + w7) - X;
+  f[2] = (A - w7) + Y;
+  f[4] = (A - w7) - Y;
+  const T D = w0 + T(2) * w1 + w2, P = w3 + w4, Q = w5 + w6;
+  f[5] = (D + w8) + (P + Q);
+  f[7] = (D + w8) - (P + Q);
+  f[6] = (D - w8) + (Q - P);
+  f[8] = (D - w8) - (Q - P);
+  double moving = (double)f[1];
+#pragma unroll
+  for (int i = 2; i < 9; ++i) moving += (double)f[i];
+  f[0] = (T)(mass - moving);
+}
+
+// Node-local quantities at time t: velocity with the half-force correction
+// (main Eq. 5), force F = G^2 rho g, and the pressure slope.
+template <typename T>
+struct NodeState {
+  T rho, ux, uy, Fx, Fy, p_lbe, dp_lbe, eta;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ NodeState<T> node_state(T rho, T jx, T jy, T gx, T gy, const Coef<T>& c) {
+  NodeState<T> s;
+  s.rho = rho;
+  s.Fx = c.g2 * rho * gx;
+  s.Fy = c.g2 * rho * gy;
+  const T inv = T(1) / rho;
+  s.ux = (jx + T(0.5) * s.Fx) * inv;
+  s.uy = (jy + T(0.5) * s.Fy) * inv;
+  eos(rho, c, s.p_lbe, s.dp_lbe);
+  s.eta = T(3) * s.p_lbe - rho;  // p_LBE = (rho + eta)/3 (main Eq. 9, alpha1 = -1, beta1 = 1)
+  return s;
+}
+
+// Moment-space collision (supplement Eq. 1) by the six-step sequence of
+// supplement Sec. IV, in place on m (pre-collision moments in, post-
+// collision moments out).  g is the stencil gradient (= grad rho, supplement
+// Eq. 61); grad p_LBE = dp_lbe g.
+template <typename T>
+__host__ __device__ __forceinline__ void collide_moments(T* m, const NodeState<T>& s, T gx, T gy,
+                                                         const Coef<T>& c) {
+  const T rho = s.rho, ux = s.ux, uy = s.uy, Fx = s.Fx, Fy = s.Fy, dp = s.dp_lbe;
+  const T ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy, u2 = ux2 + uy2, dxy = ux2 - uy2;
+  const T rux = rho * ux, ruy = rho * uy;
+  // equilibrium moments (main Eq. 3) and force moments (main Eq. 4)
+  const T meq1 = T(2) * (s.eta - rho) + T(3) * rho * u2;
+  const T meq2 = c.alpha2 * rho + c.beta2 * s.eta + rho * (T(9) * ux2 * uy2 - T(3) * u2);
+  const T meq4 = rux * (T(3) * uy2 - T(1));
+  const T meq6 = ruy * (T(3) * ux2 - T(1));
+  const T meq7 = rho * dxy;
+  const T meq8 = rho * uxy;
+  const T Fu = Fx * ux + Fy * uy;
+  const T Fm1 = T(6) * Fu;
+  const T Fm2 = T(18) * (Fx * ux * uy2 + Fy * uy * ux2) - T(6) * Fu;
+  const T Fm4 = T(3) * (Fx * uy2 + T(2) * Fy * uxy) - Fx;
+  const T Fm6 = T(3) * (Fy * ux2 + T(2) * Fx * uxy) - Fy;
+  const T Fm7 = T(2) * (Fx * ux - Fy * uy);
+  const T Fm8 = Fx * uy + Fy * ux;
+  // (1) m-bar = 2 m^eq - m;  d = m - m^eq + F_m/2
+  T d1 = m[1] - meq1 + T(0.5) * Fm1, d2 = m[2] - meq2 + T(0.5) * Fm2;
+  T d4 = m[4] - meq4 + T(0.5) * Fm4, d6 = m[6] - meq6 + T(0.5) * Fm6;
+  T d7 = m[7] - meq7 + T(0.5) * Fm7, d8 = m[8] - meq8 + T(0.5) * Fm8;
+  T b1 = T(2) * meq1 - m[1], b2 = T(2) * meq2 - m[2], b4 = T(2) * meq4 - m[4];
+  T b6 = T(2) * meq6 - m[6], b7 = T(2) * meq7 - m[7], b8 = T(2) * meq8 - m[8];
+  // (2) velocity-dependent off-diagonal part of S
+  d1 += c.k_seps_h * d2 + c.h_sq_h * (ux * d4 + uy * d6);
+  d7 += c.b_sq * (ux * d4 - uy * d6);
+  d8 += c.b_sq_h * (uy * d4 + ux * d6);
+  // (3) diagonal relaxation
+  d1 *= c.om_e;
+  d2 *= c.om_eps;
+  d4 *= c.om_q;
+  d6 *= c.om_q;
+  d7 *= c.om_p;
+  d8 *= c.om_p;
+  // (4) cubic-velocity corrections; T . grad rho + X . grad p = (T + dp X) . g
+  {
+    const T R11 = c.cR11 * u2, R17 = c.cR17 * dxy, R18 = c.cR18 * uxy;
+    const T t1x = c.cT1 * ux * (c.one_mk * ux2 - c.twok_h * uy2);
+    const T t1y = c.cT1 * uy * (c.one_mk * uy2 - c.twok_h * ux2);
+    const T x1x = c.cX1 * ux * uy2, x1y = c.cX1 * ux2 * uy;
+    b1 -= R11 * d1 + R17 * d7 + R18 * d8 + (t1x + dp * x1x) * gx + (t1y + dp * x1y) * gy;
+    const T R71 = c.cR71 * dxy, R77 = c.cR77 * u2;
+    const T t7x = c.cT7 * ux * (ux2 + c.two_b * uy2), t7y = -c.cT7 * uy * (uy2 + c.two_b * ux2);
+    const T x7x = c.cX7 * ux * uy2, x7y = -c.cX7 * ux2 * uy;
+    b7 -= R71 * d1 + R77 * d7 + (t7x + dp * x7x) * gx + (t7y + dp * x7y) * gy;
+    const T R81 = c.cR81 * uxy, R88 = c.cR88 * u2;
+    const T v8x = uy * (uy2 + T(2) * ux2), v8y = ux * (ux2 + T(2) * uy2);
+    b8 -= R81 * d1 + R88 * d8 + (c.cT8 + dp * c.cX8) * (v8x * gx + v8y * gy);
+  }
+  // (5)
+  b1 += T(2) * d1;
+  b2 += T(2) * d2;
+  b4 += T(2) * d4;
+  b6 += T(2) * d6;
+  b7 += T(2) * d7;
+  b8 += T(2) * d8;
+  // (6) epsilon^3 consistency term S Q_m with F-tilde = G g (main Eq. 14)
+  const T gg = gx * gx + gy * gy;
+  const T Q1 = T(0.5) * c.g2 * gg;  // Q_2 = -Q_1
+  b1 += c.s_e * Q1 - c.kq2 * Q1;
+  b2 -= c.s_eps * Q1;
+  b7 += c.s_p * c.g2 * (gx * gx - gy * gy) * T(1.0 / 12.0);
+  b8 += c.s_p * c.g2 * gx * gy * T(1.0 / 12.0);
+  // conserved moments: density unchanged, momentum gains F
+  m[0] = rho;
+  m[3] = m[3] + Fx;
+  m[5] = m[5] + Fy;
+  m[1] = b1;
+  m[2] = b2;
+  m[4] = b4;
+  m[6] = b6;
+  m[7] = b7;
+  m[8] = b8;
+}
+
+// f-bar from pre-collision f at one node, given the stencil gradient g.
+template <typename T>
+__host__ __device__ __forceinline__ void collide_node(T* f, T gx, T gy, const Coef<T>& c) {
+  T m[9];
+  const double mass = density_exact(f);
+  forward_moments(f, m);
+  const NodeState<T> s = node_state(m[0], m[3], m[5], gx, gy, c);
+  collide_moments(m, s, gx, gy, c);
+  inverse_moments(m, f, mass);
+}
+
+// Equilibrium populations f^eq = M^-1 m^eq(rho, u, eta(rho)).
+template <typename T>
+__host__ __device__ __forceinline__ void equilibrium_node(T rho, T ux, T uy, const Coef<T>& c, T* f) {
+  T p, dp;
+  eos(rho, c, p, dp);
+  const T eta = T(3) * p - rho;
+  const T ux2 = ux * ux, uy2 = uy * uy, u2 = ux2 + uy2;
+  T m[9];
+  m[0] = rho;
+  m[1] = T(2) * (eta - rho) + T(3) * rho * u2;
+  m[2] = c.alpha2 * rho + c.beta2 * eta + rho * (T(9) * ux2 * uy2 - T(3) * u2);
+  m[3] = rho * ux;
+  m[4] = rho * ux * (T(3) * uy2 - T(1));
+  m[5] = rho * uy;
+  m[6] = rho * uy * (T(3) * ux2 - T(1));
+  m[7] = rho * (ux2 - uy2);
+  m[8] = rho * ux * uy;
+  inverse_moments(m, f, (double)rho);
+}
+
+}  // namespace lbm

@@ -1,0 +1,258 @@
+"""Thin Python binding of the C ABI in ``include/lbm.h`` (ctypes).
+
+Every function here has the name of the C entry point it calls and only
+marshals arguments: torch tensors become device pointers, the stream comes
+from torch, status codes become ``LbmError``.  All arithmetic happens in the
+HIP library.  ``Lattice`` bundles the buffers and the context for callers
+that want torch to own the memory.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOCOEX, LBM_EHIP, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+LBM_FP32, LBM_FP16, LBM_BF16 = 0, 1, 2
+STORAGE = {"fp32": LBM_FP32, "fp16": LBM_FP16, "bf16": LBM_BF16}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"lbm status {status}: {message}")
+        self.status = status
+
+
+class lbm_params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("storage", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("s_p", ctypes.c_double), ("s_eps", ctypes.c_double),
+                ("varpi", ctypes.c_double), ("a", ctypes.c_double), ("b", ctypes.c_double),
+                ("r_gas", ctypes.c_double), ("tr", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("width", ctypes.c_double)]
+
+
+class lbm_derived(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "rho_g", "rho_l", "p0", "c_sigma", "c_w", "sigma", "width", "k_int", "k_eos", "g2", "kp", "rt",
+        "alpha2", "beta2", "k", "h", "bs", "s_p", "s_q", "s_e", "s_eps", "tc")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"HIP library {_LIB_PATH} is missing: build it with "
+                          "`python -m paper_1809_02390_amd.build` (there is no CPU fallback)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P, V, I, D = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    sig = {
+        "lbm_last_error": (ctypes.c_char_p, []),
+        "lbm_derive": (I, [P(lbm_params), P(lbm_derived)]),
+        "lbm_sigma_paper": (I, [D, D, D, D, D, P(D)]),
+        "lbm_state_bytes": (ctypes.c_size_t, [P(lbm_params)]),
+        "lbm_ref_bytes": (ctypes.c_size_t, [P(lbm_params)]),
+        "lbm_create": (I, [P(V), P(lbm_params), V, V, V, V]),
+        "lbm_set_stream": (I, [V, V]),
+        "lbm_init": (I, [V, V, V, V]),
+        "lbm_set_state": (I, [V, V]),
+        "lbm_get_state": (I, [V, V]),
+        "lbm_step": (I, [V, ctypes.c_int32]),
+        "lbm_moments": (I, [V, V, V, V, P(D)]),
+        "lbm_time": (ctypes.c_int64, [V]),
+        "lbm_get_derived": (I, [V, P(lbm_derived)]),
+        "lbm_destroy": (None, [V]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("lbm_last_error", "lbm_derive", "lbm_sigma_paper", "lbm_state_bytes", "lbm_ref_bytes",
+            "lbm_create", "lbm_set_stream", "lbm_init", "lbm_set_state", "lbm_get_state", "lbm_step",
+            "lbm_moments", "lbm_time", "lbm_get_derived", "lbm_destroy")
+
+
+def _check(status: int):
+    if status != LBM_OK:
+        raise LbmError(status, _lib.lbm_last_error().decode())
+
+
+def make_params(nx, ny, *, storage="fp32", s_p=1.0, s_eps=0.0, varpi=1.0 / 6.0, a=1.0, b=4.0,
+                r_gas=1.0, tr=0.8, sigma=0.0, width=10.0) -> lbm_params:
+    """lbm_params from keyword arguments (sigma <= 0: the paper's sound-speed rule;
+    s_eps <= 0: s_e)."""
+    st = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    return lbm_params(int(nx), int(ny), st, 0, float(s_p), float(s_eps), float(varpi), float(a), float(b),
+                      float(r_gas), float(tr), float(sigma), float(width))
+
+
+def _ptr(t, dtype=None, numel=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, has {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# Functions named after the C entry points
+# ---------------------------------------------------------------------------
+def lbm_last_error() -> str:
+    return _lib.lbm_last_error().decode()
+
+
+def lbm_derive(params: lbm_params) -> lbm_derived:
+    out = lbm_derived()
+    _check(_lib.lbm_derive(ctypes.byref(params), ctypes.byref(out)))
+    return out
+
+
+def lbm_sigma_paper(width, tr, a=1.0, b=4.0, r_gas=1.0) -> float:
+    s = ctypes.c_double()
+    _check(_lib.lbm_sigma_paper(width, tr, a, b, r_gas, ctypes.byref(s)))
+    return s.value
+
+
+def lbm_state_bytes(params: lbm_params) -> int:
+    return _lib.lbm_state_bytes(ctypes.byref(params))
+
+
+def lbm_ref_bytes(params: lbm_params) -> int:
+    return _lib.lbm_ref_bytes(ctypes.byref(params))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def lbm_create(params: lbm_params, f_a, f_b, rho_ref=None, stream=None):
+    nbytes = lbm_state_bytes(params)
+    for t, nm in ((f_a, "f_a"), (f_b, "f_b")):
+        if t is None or t.numel() * t.element_size() < nbytes:
+            raise ValueError(f"{nm} must hold at least {nbytes} bytes")
+    ctx = ctypes.c_void_p()
+    _check(_lib.lbm_create(ctypes.byref(ctx), ctypes.byref(params), _ptr(f_a, name="f_a"),
+                           _ptr(f_b, name="f_b"), _ptr(rho_ref, name="rho_ref"), _stream_handle(stream)))
+    return ctx
+
+
+def lbm_set_stream(ctx, stream=None):
+    _check(_lib.lbm_set_stream(ctx, _stream_handle(stream)))
+
+
+def lbm_init(ctx, rho0, ux0=None, uy0=None, n=None):
+    _check(_lib.lbm_init(ctx, _ptr(rho0, torch.float32, n, "rho0"), _ptr(ux0, torch.float32, n, "ux0"),
+                         _ptr(uy0, torch.float32, n, "uy0")))
+
+
+def lbm_set_state(ctx, f, n=None):
+    _check(_lib.lbm_set_state(ctx, _ptr(f, torch.float32, None if n is None else 9 * n, "f")))
+
+
+def lbm_get_state(ctx, f, n=None):
+    _check(_lib.lbm_get_state(ctx, _ptr(f, torch.float32, None if n is None else 9 * n, "f")))
+
+
+def lbm_step(ctx, n: int):
+    _check(_lib.lbm_step(ctx, int(n)))
+
+
+def lbm_moments(ctx, rho=None, ux=None, uy=None, totals=True, n=None):
+    tot = (ctypes.c_double * 3)()
+    _check(_lib.lbm_moments(ctx, _ptr(rho, torch.float32, n, "rho"), _ptr(ux, torch.float32, n, "ux"),
+                            _ptr(uy, torch.float32, n, "uy"), tot if totals else None))
+    return tuple(tot) if totals else None
+
+
+def lbm_time(ctx) -> int:
+    return int(_lib.lbm_time(ctx))
+
+
+def lbm_get_derived(ctx) -> lbm_derived:
+    out = lbm_derived()
+    _check(_lib.lbm_get_derived(ctx, ctypes.byref(out)))
+    return out
+
+
+def lbm_destroy(ctx):
+    _lib.lbm_destroy(ctx)
+
+
+# ---------------------------------------------------------------------------
+# Convenience owner of buffers + context
+# ---------------------------------------------------------------------------
+class Lattice:
+    """Torch-owned A/B buffers plus a library context on the current device."""
+
+    def __init__(self, nx, ny, device="cuda", stream=None, **kw):
+        self.params = make_params(nx, ny, **kw)
+        self.nx, self.ny, self.n = nx, ny, nx * ny
+        nbytes = lbm_state_bytes(self.params)
+        if nbytes == 0:
+            lbm_derive(self.params)  # raises with the validation message
+        self.f_a = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.f_b = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        rb = lbm_ref_bytes(self.params)
+        self.rho_ref = torch.empty(rb, dtype=torch.uint8, device=device) if rb else None
+        self.ctx = lbm_create(self.params, self.f_a, self.f_b, self.rho_ref, stream)
+        self.derived = lbm_get_derived(self.ctx)
+
+    def init(self, rho0, ux0=None, uy0=None):
+        dev = self.f_a.device
+        conv = lambda a: None if a is None else torch.as_tensor(a, dtype=torch.float32).to(dev).contiguous()
+        self._keep = [conv(rho0), conv(ux0), conv(uy0)]
+        lbm_init(self.ctx, *self._keep, n=self.n)
+        return self
+
+    def set_state(self, f):
+        f = torch.as_tensor(f, dtype=torch.float32).to(self.f_a.device).contiguous()
+        lbm_set_state(self.ctx, f, n=self.n)
+        self._keep = [f]
+        return self
+
+    def state(self):
+        f = torch.empty((9, self.ny, self.nx), dtype=torch.float32, device=self.f_a.device)
+        lbm_get_state(self.ctx, f, n=self.n)
+        return f
+
+    def step(self, n=1):
+        lbm_step(self.ctx, n)
+        return self
+
+    def moments(self, fields=True):
+        dev = self.f_a.device
+        if fields:
+            rho, ux, uy = (torch.empty((self.ny, self.nx), dtype=torch.float32, device=dev) for _ in range(3))
+            tot = lbm_moments(self.ctx, rho, ux, uy, True, n=self.n)
+            return rho, ux, uy, tot
+        return lbm_moments(self.ctx, None, None, None, True, n=self.n)
+
+    @property
+    def time(self):
+        return lbm_time(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
