@@ -17,7 +17,12 @@ struct Coef {
   T g2;        // G'^2 (force strength, main Eq. 12)
   T kp, rt;    // K' = K_EOS and R T of the CS pressure (main Eq. 20)
   T a, b4;     // a and b/4
+  T kprt;      // K' R T
+  T e_rho;     // G'^2/2 - K' a   : p_LBE = rho (K' R T Z + e_rho rho)
+  T de_rho;    // G'^2 - 2 K' a   : d p_LBE / d rho = K' R T (rho Z)' + de_rho rho
   T alpha2, beta2;
+  // 1 - s for the rows without off-diagonal coupling
+  T one_m_seps, one_m_sq;
   // step (2) of supplement Sec. IV
   T k_seps_h;  // k s_eps / 2
   T h_sq_h;    // h s_q / 2
@@ -25,13 +30,27 @@ struct Coef {
   T b_sq_h;    // b s_q / 2
   // step (3): 1 - s/2
   T om_e, om_eps, om_q, om_p;
+  T two_om_e, two_om_p;  // 2 (1 - s/2)
   // step (4): nonzero entries of R, T, X (supplement Eqs. 34, 37, 40)
   T cR11, cR17, cR18, cT1, one_mk, twok_h, cX1;
+  T cT1a, cT1b;  // cT1 (1 - k), cT1 (2k + h)
   T cR71, cR77, cT7, two_b, cX7;
   T cR81, cR88, cT8, cX8;
   // step (6)
   T s_e, kq2, s_eps, s_p;  // kq2 = k (s_e/2 - 1) s_eps
+  T q1, q7;                // (s_e - kq2) G'^2 / 2 and s_p G'^2 / 12
 };
+
+// Reciprocal: the one-instruction v_rcp_f32 (1 ulp) on the device, a
+// division elsewhere.  Every kernel uses the same function, so forward steps
+// and recomputations agree bit for bit.
+template <typename T>
+__host__ __device__ __forceinline__ T recip(T x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if constexpr (sizeof(T) == 4) return __builtin_amdgcn_rcpf(x);
+#endif
+  return T(1) / x;
+}
 
 // rho = sum_i f_i accumulated in FP64: for nine populations of one node the
 // double sum is exact, so every density (tile, ring, collision) is the same
@@ -67,12 +86,12 @@ __host__ __device__ __forceinline__ void stencil(T rE, T rN, T rW, T rS, T rNE, 
 template <typename T>
 __host__ __device__ __forceinline__ void eos(T rho, const Coef<T>& c, T& p_lbe, T& dp_lbe) {
   const T v = c.b4 * rho;
-  const T iw = T(1) / (T(1) - v);
+  const T iw = recip(T(1) - v);
   const T iw3 = iw * iw * iw;
   const T z = (T(1) + v * (T(1) + v * (T(1) - v))) * iw3;
   const T dz = (T(1) + v * (T(4) + v * (T(4) + v * (v - T(4))))) * (iw3 * iw);
-  p_lbe = c.kp * rho * (c.rt * z - c.a * rho) + T(0.5) * c.g2 * rho * rho;
-  dp_lbe = c.kp * (c.rt * dz - T(2) * c.a * rho) + c.g2 * rho;
+  p_lbe = rho * (c.kprt * z + c.e_rho * rho);
+  dp_lbe = c.kprt * dz + c.de_rho * rho;
 }
 
 // m = M f (supplement Eq. 4) as an add/subtract tree; m[0] is density(f).
@@ -132,7 +151,7 @@ __host__ __device__ __forceinline__ NodeState<T> node_state(T rho, T jx, T jy, T
   s.rho = rho;
   s.Fx = c.g2 * rho * gx;
   s.Fy = c.g2 * rho * gy;
-  const T inv = T(1) / rho;
+  const T inv = recip(rho);
   s.ux = (jx + T(0.5) * s.Fx) * inv;
   s.uy = (jy + T(0.5) * s.Fy) * inv;
   eos(rho, c, s.p_lbe, s.dp_lbe);
@@ -149,85 +168,62 @@ __host__ __device__ __forceinline__ void collide_moments(T* m, const NodeState<T
                                                          const Coef<T>& c) {
   const T rho = s.rho, ux = s.ux, uy = s.uy, Fx = s.Fx, Fy = s.Fy, dp = s.dp_lbe;
   const T ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy, u2 = ux2 + uy2, dxy = ux2 - uy2;
-  const T rux = rho * ux, ruy = rho * uy;
-  // equilibrium moments (main Eq. 3) and force moments (main Eq. 4)
+  // equilibrium moments m^eq (main Eq. 3) and half force moments F_m/2 (main Eq. 4)
   const T meq1 = T(2) * (s.eta - rho) + T(3) * rho * u2;
   const T meq2 = c.alpha2 * rho + c.beta2 * s.eta + rho * (T(9) * ux2 * uy2 - T(3) * u2);
-  const T meq4 = rux * (T(3) * uy2 - T(1));
-  const T meq6 = ruy * (T(3) * ux2 - T(1));
+  const T meq4 = rho * ux * (T(3) * uy2 - T(1));
+  const T meq6 = rho * uy * (T(3) * ux2 - T(1));
   const T meq7 = rho * dxy;
   const T meq8 = rho * uxy;
-  const T Fu = Fx * ux + Fy * uy;
-  const T Fm1 = T(6) * Fu;
-  const T Fm2 = T(18) * (Fx * ux * uy2 + Fy * uy * ux2) - T(6) * Fu;
-  const T Fm4 = T(3) * (Fx * uy2 + T(2) * Fy * uxy) - Fx;
-  const T Fm6 = T(3) * (Fy * ux2 + T(2) * Fx * uxy) - Fy;
-  const T Fm7 = T(2) * (Fx * ux - Fy * uy);
-  const T Fm8 = Fx * uy + Fy * ux;
-  // (1) m-bar = 2 m^eq - m;  d = m - m^eq + F_m/2
-  T d1 = m[1] - meq1 + T(0.5) * Fm1, d2 = m[2] - meq2 + T(0.5) * Fm2;
-  T d4 = m[4] - meq4 + T(0.5) * Fm4, d6 = m[6] - meq6 + T(0.5) * Fm6;
-  T d7 = m[7] - meq7 + T(0.5) * Fm7, d8 = m[8] - meq8 + T(0.5) * Fm8;
-  T b1 = T(2) * meq1 - m[1], b2 = T(2) * meq2 - m[2], b4 = T(2) * meq4 - m[4];
-  T b6 = T(2) * meq6 - m[6], b7 = T(2) * meq7 - m[7], b8 = T(2) * meq8 - m[8];
-  // (2) velocity-dependent off-diagonal part of S
-  d1 += c.k_seps_h * d2 + c.h_sq_h * (ux * d4 + uy * d6);
-  d7 += c.b_sq * (ux * d4 - uy * d6);
-  d8 += c.b_sq_h * (uy * d4 + ux * d6);
-  // (3) diagonal relaxation
-  d1 *= c.om_e;
-  d2 *= c.om_eps;
-  d4 *= c.om_q;
-  d6 *= c.om_q;
-  d7 *= c.om_p;
-  d8 *= c.om_p;
+  const T Fu3 = T(3) * (Fx * ux + Fy * uy);
+  const T hF1 = Fu3;
+  const T hF2 = T(9) * (Fx * ux * uy2 + Fy * uy * ux2) - Fu3;
+  const T hF4 = T(1.5) * (Fx * uy2 + T(2) * Fy * uxy) - T(0.5) * Fx;
+  const T hF6 = T(1.5) * (Fy * ux2 + T(2) * Fx * uxy) - T(0.5) * Fy;
+  const T hF7 = Fx * ux - Fy * uy;
+  const T hF8 = T(0.5) * (Fx * uy + Fy * ux);
+  // (1) d = m - m^eq + F_m/2; the post-collision moment starts from
+  //     2 m^eq - m = (m^eq + F_m/2) - d
+  const T d1 = m[1] - meq1 + hF1, d2 = m[2] - meq2 + hF2, d4 = m[4] - meq4 + hF4;
+  const T d6 = m[6] - meq6 + hF6, d7 = m[7] - meq7 + hF7, d8 = m[8] - meq8 + hF8;
+  // (2) off-diagonal part of S, (3) diagonal relaxation: D = (1 - s/2)(d + N d)
+  const T D1 = c.om_e * (d1 + c.k_seps_h * d2 + c.h_sq_h * (ux * d4 + uy * d6));
+  const T D7 = c.om_p * (d7 + c.b_sq * (ux * d4 - uy * d6));
+  const T D8 = c.om_p * (d8 + c.b_sq_h * (uy * d4 + ux * d6));
   // (4) cubic-velocity corrections; T . grad rho + X . grad p = (T + dp X) . g
-  {
-    const T R11 = c.cR11 * u2, R17 = c.cR17 * dxy, R18 = c.cR18 * uxy;
-    const T t1x = c.cT1 * ux * (c.one_mk * ux2 - c.twok_h * uy2);
-    const T t1y = c.cT1 * uy * (c.one_mk * uy2 - c.twok_h * ux2);
-    const T x1x = c.cX1 * ux * uy2, x1y = c.cX1 * ux2 * uy;
-    b1 -= R11 * d1 + R17 * d7 + R18 * d8 + (t1x + dp * x1x) * gx + (t1y + dp * x1y) * gy;
-    const T R71 = c.cR71 * dxy, R77 = c.cR77 * u2;
-    const T t7x = c.cT7 * ux * (ux2 + c.two_b * uy2), t7y = -c.cT7 * uy * (uy2 + c.two_b * ux2);
-    const T x7x = c.cX7 * ux * uy2, x7y = -c.cX7 * ux2 * uy;
-    b7 -= R71 * d1 + R77 * d7 + (t7x + dp * x7x) * gx + (t7y + dp * x7y) * gy;
-    const T R81 = c.cR81 * uxy, R88 = c.cR88 * u2;
-    const T v8x = uy * (uy2 + T(2) * ux2), v8y = ux * (ux2 + T(2) * uy2);
-    b8 -= R81 * d1 + R88 * d8 + (c.cT8 + dp * c.cX8) * (v8x * gx + v8y * gy);
-  }
-  // (5)
-  b1 += T(2) * d1;
-  b2 += T(2) * d2;
-  b4 += T(2) * d4;
-  b6 += T(2) * d6;
-  b7 += T(2) * d7;
-  b8 += T(2) * d8;
-  // (6) epsilon^3 consistency term S Q_m with F-tilde = G g (main Eq. 14)
+  const T R11 = c.cR11 * u2, R17 = c.cR17 * dxy, R18 = c.cR18 * uxy;
+  const T t1x = ux * (c.cT1a * ux2 - c.cT1b * uy2), t1y = uy * (c.cT1a * uy2 - c.cT1b * ux2);
+  const T x1x = c.cX1 * uxy * uy, x1y = c.cX1 * uxy * ux;
+  const T corr1 = R11 * D1 + R17 * D7 + R18 * D8 + (t1x + dp * x1x) * gx + (t1y + dp * x1y) * gy;
+  const T R71 = c.cR71 * dxy, R77 = c.cR77 * u2;
+  const T t7x = c.cT7 * ux * (ux2 + c.two_b * uy2), t7y = -c.cT7 * uy * (uy2 + c.two_b * ux2);
+  const T x7x = c.cX7 * uxy * uy, x7y = -c.cX7 * uxy * ux;
+  const T corr7 = R71 * D1 + R77 * D7 + (t7x + dp * x7x) * gx + (t7y + dp * x7y) * gy;
+  const T R81 = c.cR81 * uxy, R88 = c.cR88 * u2;
+  const T v8x = uy * (uy2 + T(2) * ux2), v8y = ux * (ux2 + T(2) * uy2);
+  const T corr8 = R81 * D1 + R88 * D8 + (c.cT8 + dp * c.cX8) * (v8x * gx + v8y * gy);
+  // (5) m-bar = (m^eq + F_m/2) - d + 2 D - corrections; rows 2, 4, 6 have no
+  //     coupling, so -d + 2 D = (1 - s) d there.  (6) adds S Q_m with
+  //     F-tilde = G g (main Eq. 14): Q_1 = -Q_2 = G^2 |g|^2 / 2.
   const T gg = gx * gx + gy * gy;
-  const T Q1 = T(0.5) * c.g2 * gg;  // Q_2 = -Q_1
-  b1 += c.s_e * Q1 - c.kq2 * Q1;
-  b2 -= c.s_eps * Q1;
-  b7 += c.s_p * c.g2 * (gx * gx - gy * gy) * T(1.0 / 12.0);
-  b8 += c.s_p * c.g2 * gx * gy * T(1.0 / 12.0);
-  // conserved moments: density unchanged, momentum gains F
   m[0] = rho;
-  m[3] = m[3] + Fx;
+  m[1] = (meq1 + hF1) - d1 + T(2) * D1 - corr1 + c.q1 * gg;
+  m[2] = (meq2 + hF2) + c.one_m_seps * d2 - c.s_eps * T(0.5) * c.g2 * gg;
+  m[3] = m[3] + Fx;  // momentum gains F, density unchanged
+  m[4] = (meq4 + hF4) + c.one_m_sq * d4;
   m[5] = m[5] + Fy;
-  m[1] = b1;
-  m[2] = b2;
-  m[4] = b4;
-  m[6] = b6;
-  m[7] = b7;
-  m[8] = b8;
+  m[6] = (meq6 + hF6) + c.one_m_sq * d6;
+  m[7] = (meq7 + hF7) - d7 + T(2) * D7 - corr7 + c.q7 * (gx * gx - gy * gy);
+  m[8] = (meq8 + hF8) - d8 + T(2) * D8 - corr8 + c.q7 * (gx * gy);
 }
 
-// f-bar from pre-collision f at one node, given the stencil gradient g.
+// f-bar from pre-collision f at one node, given its exact mass
+// (density_exact(f)) and the stencil gradient g.
 template <typename T>
-__host__ __device__ __forceinline__ void collide_node(T* f, T gx, T gy, const Coef<T>& c) {
+__host__ __device__ __forceinline__ void collide_node(T* f, double mass, T gx, T gy, const Coef<T>& c) {
   T m[9];
-  const double mass = density_exact(f);
   forward_moments(f, m);
+  m[0] = (T)mass;
   const NodeState<T> s = node_state(m[0], m[3], m[5], gx, gy, c);
   collide_moments(m, s, gx, gy, c);
   inverse_moments(m, f, mass);

@@ -61,119 +61,234 @@ __device__ __forceinline__ void pull9(const float* __restrict__ src, size_t N, i
   f[8] = src[8 * N + rp + xm];
 }
 
-__device__ __forceinline__ float pulled_density(const float* __restrict__ src, size_t N, int nx, int ny, int gx,
-                                                int gy) {
-  const int xm = gx == 0 ? nx - 1 : gx - 1, xp = gx == nx - 1 ? 0 : gx + 1;
-  const int ym = gy == 0 ? ny - 1 : gy - 1, yp = gy == ny - 1 ? 0 : gy + 1;
-  float f[9];
-  pull9(src, N, nx, gx, xm, xp, gy, ym, yp, f);
-  return density(f);
+// The same pull with 32-bit byte offsets from per-plane base pointers (the
+// bases are uniform, so the loads use a scalar base plus one vector offset).
+// A node is addressed by its three row offsets (row * nx * 4 for rows y,
+// y-1, y+1) and three column offsets (4 x for x, x-1, x+1).
+struct NodeAddr {
+  unsigned r0, rm, rp, c0, cm, cp;
+};
+
+__device__ __forceinline__ NodeAddr node_addr(int x, int y, int nx, int ny) {
+  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+  const unsigned rb = 4u * (unsigned)nx;
+  return {rb * (unsigned)y, rb * (unsigned)ym, rb * (unsigned)yp, 4u * (unsigned)x, 4u * (unsigned)xm,
+          4u * (unsigned)xp};
+}
+
+__device__ __forceinline__ float ldb(const char* __restrict__ base, unsigned off) {
+  return *reinterpret_cast<const float*>(base + off);
+}
+
+struct Planes {
+  const char* p[9];
+};
+
+__device__ __forceinline__ Planes planes(const float* src, size_t N) {
+  Planes P;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) P.p[i] = reinterpret_cast<const char*>(src + (size_t)i * N);
+  return P;
+}
+
+struct OutPlanes {
+  char* p[9];
+};
+
+__device__ __forceinline__ OutPlanes out_planes(float* dst, size_t N) {
+  OutPlanes P;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) P.p[i] = reinterpret_cast<char*>(dst + (size_t)i * N);
+  return P;
+}
+
+__device__ __forceinline__ void pull9b(const Planes& P, const NodeAddr& a, float* f) {
+  f[0] = ldb(P.p[0], a.r0 + a.c0);
+  f[1] = ldb(P.p[1], a.r0 + a.cm);
+  f[2] = ldb(P.p[2], a.rm + a.c0);
+  f[3] = ldb(P.p[3], a.r0 + a.cp);
+  f[4] = ldb(P.p[4], a.rp + a.c0);
+  f[5] = ldb(P.p[5], a.rm + a.cm);
+  f[6] = ldb(P.p[6], a.rm + a.cp);
+  f[7] = ldb(P.p[7], a.rp + a.cp);
+  f[8] = ldb(P.p[8], a.rp + a.cm);
+}
+
+// Tile order across the eight XCDs of the chip: workgroups are dealt to the
+// XCDs round-robin by dispatch index, so dispatch b runs on XCD b % 8.  Give
+// each XCD one contiguous run of tiles (in raster order) so that the tiles
+// whose halo lines overlap share that XCD's L2.  A bijection onto
+// [0, ntiles) for any ntiles.
+__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
+  const int q = ntiles >> 3, r = ntiles & 7, xcd = b & 7, local = b >> 3;
+  return xcd * q + (xcd < r ? xcd : r) + local;
 }
 
 // ---------------------------------------------------------------------------
 // Fused step: tile of TX x TY nodes per workgroup of TX x WY threads; each
 // thread owns NPT = TY/WY nodes of one column.  The tile plus a one-node
 // ring of densities is staged in LDS for the force stencil; ring nodes pull
-// their own populations (cache hits of the neighbouring tiles' lines).
+// their own populations (L2 hits: the neighbouring tiles run on the same XCD).
 // ---------------------------------------------------------------------------
-constexpr int TX = 64, TY = 16, WY = 4, NPT = TY / WY, LW = TX + 2, NRING = 2 * LW + 2 * TY;
-static_assert(NRING <= TX * WY, "one ring node per thread");
+template <int TX_, int TY_, int WY_>
+struct TileShape {
+  static constexpr int TX = TX_, TY = TY_, WY = WY_, NPT = TY / WY, LW = TX + 2;
+  static constexpr int NRING = 2 * LW + 2 * TY, NTHREADS = TX * WY, LDS = (TY + 2) * LW;
+  static_assert(TY % WY == 0, "rows per thread");
+  static_assert(NRING <= NTHREADS, "one ring node per thread");
+};
 
-// Density tile of the workgroup at (x0, y0) into srho[(TY+2)][LW]; fills the
-// caller's registers with the pulled populations of its NPT own nodes.
-__device__ __forceinline__ void load_tile(const float* __restrict__ src, size_t N, int nx, int ny, int x0, int y0,
-                                          float (&f)[NPT][9], float* srho) {
-  const int tx = threadIdx.x, ty = threadIdx.y;
-  const int xw = wrap(x0 + tx, nx);
-  const int xm = xw == 0 ? nx - 1 : xw - 1, xp = xw == nx - 1 ? 0 : xw + 1;
-#pragma unroll
-  for (int k = 0; k < NPT; ++k) {
-    const int yw = wrap(y0 + ty + k * WY, ny);
-    const int ym = yw == 0 ? ny - 1 : yw - 1, yp = yw == ny - 1 ? 0 : yw + 1;
-    pull9(src, N, nx, xw, xm, xp, yw, ym, yp, f[k]);
-    srho[(ty + k * WY + 1) * LW + tx + 1] = density(f[k]);
+// Tile of the step kernel (TX, TY, WY); a compile-time tuning knob.
+#ifndef LBM_STEP_TILE
+#define LBM_STEP_TILE 128, 8, 4
+#endif
+using StepTile = TileShape<LBM_STEP_TILE>;
+
+// Coordinates (hx, hy) in the (TY+2) x LW density tile of ring slot t.
+template <class S>
+__device__ __forceinline__ void ring_slot(int t, int& hx, int& hy) {
+  if (t < S::LW) {
+    hx = t, hy = 0;
+  } else if (t < 2 * S::LW) {
+    hx = t - S::LW, hy = S::TY + 1;
+  } else if (t < 2 * S::LW + S::TY) {
+    hx = 0, hy = t - 2 * S::LW + 1;
+  } else {
+    hx = S::LW - 1, hy = t - 2 * S::LW - S::TY + 1;
   }
-  const int tid = ty * TX + tx;
-  if (tid < NRING) {
+}
+
+// Populations of one tile held in registers: NPT own nodes per thread plus,
+// for the first NRING threads, one ring node.
+template <class S>
+struct TileRegs {
+  float f[S::NPT][9];
+  float fr[9];
+};
+
+// Issue the loads of the tile at (x0, y0); ring loads first.
+template <class S>
+__device__ __forceinline__ void issue_tile(const Planes& P, int nx, int ny, int x0, int y0, TileRegs<S>& R) {
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * S::TX + tx;
+  if (tid < S::NRING) {
     int hx, hy;
-    if (tid < LW) {
-      hx = tid, hy = 0;
-    } else if (tid < 2 * LW) {
-      hx = tid - LW, hy = TY + 1;
-    } else if (tid < 2 * LW + TY) {
-      hx = 0, hy = tid - 2 * LW + 1;
-    } else {
-      hx = LW - 1, hy = tid - 2 * LW - TY + 1;
-    }
-    srho[hy * LW + hx] = pulled_density(src, N, nx, ny, wrap(x0 + hx - 1, nx), wrap(y0 + hy - 1, ny));
+    ring_slot<S>(tid, hx, hy);
+    pull9b(P, node_addr(wrap(x0 + hx - 1, nx), wrap(y0 + hy - 1, ny), nx, ny), R.fr);
+  }
+  const int xw = wrap(x0 + tx, nx);
+#pragma unroll
+  for (int k = 0; k < S::NPT; ++k) pull9b(P, node_addr(xw, wrap(y0 + ty + k * S::WY, ny), nx, ny), R.f[k]);
+}
+
+// Densities of the tile and its ring into srho[(TY+2)][LW]; the exact
+// (FP64) masses of the own nodes are kept for the collision.
+template <class S>
+__device__ __forceinline__ void stage_density(const TileRegs<S>& R, double (&mass)[S::NPT], float* srho) {
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * S::TX + tx;
+#pragma unroll
+  for (int k = 0; k < S::NPT; ++k) {
+    mass[k] = density_exact(R.f[k]);
+    srho[(ty + k * S::WY + 1) * S::LW + tx + 1] = (float)mass[k];
+  }
+  if (tid < S::NRING) {
+    int hx, hy;
+    ring_slot<S>(tid, hx, hy);
+    srho[hy * S::LW + hx] = density(R.fr);
   }
 }
 
+template <class S>
 __device__ __forceinline__ void tile_gradient(const float* srho, int hx, int hy, float& gx, float& gy) {
-  const float* r = srho + hy * LW + hx;
-  stencil(r[1], r[LW], r[-1], r[-LW], r[LW + 1], r[LW - 1], r[-LW - 1], r[-LW + 1], gx, gy);
+  const float* r = srho + hy * S::LW + hx;
+  stencil(r[1], r[S::LW], r[-1], r[-S::LW], r[S::LW + 1], r[S::LW - 1], r[-S::LW - 1], r[-S::LW + 1], gx, gy);
 }
 
-__global__ __launch_bounds__(TX* WY) void step_f32(const float* __restrict__ src, float* __restrict__ dst, int nx,
-                                                   int ny, Coef<float> c) {
-  __shared__ float srho[(TY + 2) * LW];
-  const size_t N = (size_t)nx * ny;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-  float f[NPT][9];
-  load_tile(src, N, nx, ny, x0, y0, f, srho);
-  __syncthreads();
+// Collide the own nodes of the tile at (x0, y0) and store f-bar at the node.
+template <class S>
+__device__ __forceinline__ void collide_tile(TileRegs<S>& R, const double (&mass)[S::NPT], const float* srho,
+                                             const OutPlanes& Q, int nx, int ny, int x0, int y0,
+                                             const Coef<float>& c) {
   const int x = x0 + threadIdx.x;
+  if (x >= nx) return;
+  const unsigned rb = 4u * (unsigned)nx;
 #pragma unroll
-  for (int k = 0; k < NPT; ++k) {
-    const int ly = threadIdx.y + k * WY, y = y0 + ly;
-    if (x >= nx || y >= ny) continue;
+  for (int k = 0; k < S::NPT; ++k) {
+    const int ly = threadIdx.y + k * S::WY, y = y0 + ly;
+    if (y >= ny) break;
     float gx, gy;
-    tile_gradient(srho, threadIdx.x + 1, ly + 1, gx, gy);
-    collide_node(f[k], gx, gy, c);
-    const size_t o = (size_t)y * nx + x;
+    tile_gradient<S>(srho, threadIdx.x + 1, ly + 1, gx, gy);
+    collide_node(R.f[k], mass[k], gx, gy, c);
+    const unsigned o = rb * (unsigned)y + 4u * (unsigned)x;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(f[k][i], dst + i * N + o);
+    for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(R.f[k][i], reinterpret_cast<float*>(Q.p[i] + o));
   }
+}
+
+// Step kernel: one tile per workgroup, tiles ordered across the XCDs by
+// xcd_tile so that neighbouring tiles (whose halo lines overlap) run on the
+// same XCD and share its L2.
+template <class S>
+__global__ __launch_bounds__(S::NTHREADS) void step_f32(const float* __restrict__ src, float* __restrict__ dst,
+                                                        int nx, int ny, int ntx, int ntiles, Coef<float> c) {
+  __shared__ float srho[S::LDS];
+  const size_t N = (size_t)nx * ny;
+  const int tile = xcd_tile(blockIdx.x, ntiles);
+  const int x0 = (tile % ntx) * S::TX, y0 = (tile / ntx) * S::TY;
+  TileRegs<S> R;
+  double mass[S::NPT];
+  issue_tile<S>(planes(src, N), nx, ny, x0, y0, R);
+  stage_density<S>(R, mass, srho);
+  __syncthreads();
+  collide_tile<S>(R, mass, srho, out_planes(dst, N), nx, ny, x0, y0, c);
 }
 
 // Moments: rho and u of main Eq. 5 plus per-workgroup FP64 partial sums of
 // mass and lattice momentum (reduced in a fixed order).
-__global__ __launch_bounds__(TX* WY) void moments_f32(const float* __restrict__ src, float* __restrict__ rho_out,
-                                                      float* __restrict__ ux_out, float* __restrict__ uy_out,
-                                                      double* __restrict__ partials, int nx, int ny,
-                                                      Coef<float> c) {
-  __shared__ float srho[(TY + 2) * LW];
-  __shared__ double sred[3][TX * WY];
+using MomTile = TileShape<64, 16, 4>;
+
+__global__ __launch_bounds__(MomTile::NTHREADS) void moments_f32(const float* __restrict__ src,
+                                                                 float* __restrict__ rho_out,
+                                                                 float* __restrict__ ux_out,
+                                                                 float* __restrict__ uy_out,
+                                                                 double* __restrict__ partials, int nx, int ny,
+                                                                 int ntx, Coef<float> c) {
+  using S = MomTile;
+  __shared__ float srho[S::LDS];
+  __shared__ double sred[3][S::NTHREADS];
   const size_t N = (size_t)nx * ny;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-  float f[NPT][9];
-  load_tile(src, N, nx, ny, x0, y0, f, srho);
+  const int x0 = (blockIdx.x % ntx) * S::TX, y0 = (blockIdx.x / ntx) * S::TY;
+  TileRegs<S> R;
+  double mass[S::NPT];
+  issue_tile<S>(planes(src, N), nx, ny, x0, y0, R);
+  stage_density<S>(R, mass, srho);
   __syncthreads();
+  auto& f = R.f;
   const int x = x0 + threadIdx.x;
   double sm = 0.0, sx = 0.0, sy = 0.0;
 #pragma unroll
-  for (int k = 0; k < NPT; ++k) {
-    const int ly = threadIdx.y + k * WY, y = y0 + ly;
+  for (int k = 0; k < S::NPT; ++k) {
+    const int ly = threadIdx.y + k * S::WY, y = y0 + ly;
     if (x >= nx || y >= ny) continue;
     float m[9];
     forward_moments(f[k], m);
     float gx, gy;
-    tile_gradient(srho, threadIdx.x + 1, ly + 1, gx, gy);
+    tile_gradient<S>(srho, threadIdx.x + 1, ly + 1, gx, gy);
     const NodeState<float> s = node_state(m[0], m[3], m[5], gx, gy, c);
     const size_t o = (size_t)y * nx + x;
     if (rho_out) rho_out[o] = m[0];
     if (ux_out) ux_out[o] = s.ux;
     if (uy_out) uy_out[o] = s.uy;
-    sm += (double)m[0];
+    sm += mass[k];
     sx += (double)m[3];
     sy += (double)m[5];
   }
-  const int tid = threadIdx.y * TX + threadIdx.x;
+  const int tid = threadIdx.y * S::TX + threadIdx.x;
   sred[0][tid] = sm;
   sred[1][tid] = sx;
   sred[2][tid] = sy;
   __syncthreads();
-  for (int w = TX * WY / 2; w > 0; w >>= 1) {
+  for (int w = S::NTHREADS / 2; w > 0; w >>= 1) {
     if (tid < w) {
       sred[0][tid] += sred[0][tid + w];
       sred[1][tid] += sred[1][tid + w];
@@ -181,7 +296,7 @@ __global__ __launch_bounds__(TX* WY) void moments_f32(const float* __restrict__ 
     }
     __syncthreads();
   }
-  if (tid < 3) partials[(size_t)(blockIdx.y * gridDim.x + blockIdx.x) * 3 + tid] = sred[tid][0];
+  if (tid < 3) partials[(size_t)blockIdx.x * 3 + tid] = sred[tid][0];
 }
 
 constexpr int RED = 256;
@@ -276,6 +391,9 @@ Coef<float> make_coef(const lbm_derived& d, double varpi, double a, double b) {
   c.rt = d.rt;
   c.a = a;
   c.b4 = 0.25 * b;
+  c.kprt = d.kp * d.rt;
+  c.e_rho = 0.5 * d.g2 - d.kp * a;
+  c.de_rho = d.g2 - 2.0 * d.kp * a;
   c.alpha2 = d.alpha2;
   c.beta2 = d.beta2;
   c.k_seps_h = 0.5 * k * seps;
@@ -286,6 +404,10 @@ Coef<float> make_coef(const lbm_derived& d, double varpi, double a, double b) {
   c.om_eps = 1.0 - 0.5 * seps;
   c.om_q = 1.0 - 0.5 * sq;
   c.om_p = 1.0 - 0.5 * sp;
+  c.two_om_e = 2.0 - se;
+  c.two_om_p = 2.0 - sp;
+  c.one_m_seps = 1.0 - seps;
+  c.one_m_sq = 1.0 - sq;
   c.cR11 = -(se / (4.0 * varpi)) * (9.0 * (1.0 - k) - 2.0 * (3.0 * k + h));
   c.cR17 = -(3.0 * sp * (2.0 - se)) / (4.0 * (2.0 - sp)) * (9.0 * (1.0 - k) + 2.0 * (3.0 * k + h));
   c.cR18 = 12.0 * sp * (2.0 - se) / (2.0 - sp) * (3.0 * k + h);
@@ -293,6 +415,8 @@ Coef<float> make_coef(const lbm_derived& d, double varpi, double a, double b) {
   c.one_mk = 1.0 - k;
   c.twok_h = 2.0 * k + h;
   c.cX1 = 4.5 * (2.0 - se) * (2.0 * k + h);
+  c.cT1a = c.cT1 * (1.0 - k);
+  c.cT1b = c.cT1 * (2.0 * k + h);
   c.cR71 = -(se * (2.0 - sp)) / (4.0 * varpi * (2.0 - se)) * (3.0 - 4.0 * bs);
   c.cR77 = -(3.0 * sp / 4.0) * (3.0 + 4.0 * bs);
   c.cT7 = 0.5 * (2.0 - sp);
@@ -306,6 +430,8 @@ Coef<float> make_coef(const lbm_derived& d, double varpi, double a, double b) {
   c.kq2 = k * (0.5 * se - 1.0) * seps;
   c.s_eps = seps;
   c.s_p = sp;
+  c.q1 = (se - c.kq2) * 0.5 * d.g2;
+  c.q7 = sp * d.g2 / 12.0;
   Coef<float> f;
   const double* src = reinterpret_cast<const double*>(&c);
   float* dstp = reinterpret_cast<float*>(&f);
@@ -330,14 +456,17 @@ struct lbm_ctx {
   int64_t t;
   hipStream_t stream;
   int device;
-  int nblocks;    // workgroups of the tile grid
+  int nblocks;    // workgroups of the moments tile grid
   double* scratch;  // nblocks*3 partials, then 3 totals
   int* flag;
 };
 
 namespace {
 
-dim3 tile_grid(int nx, int ny) { return dim3((nx + TX - 1) / TX, (ny + TY - 1) / TY); }
+template <class S>
+int tiles_x(int nx) { return (nx + S::TX - 1) / S::TX; }
+template <class S>
+int tiles_total(int nx, int ny) { return tiles_x<S>(nx) * ((ny + S::TY - 1) / S::TY); }
 
 int check_ctx(const lbm_ctx* ctx, bool need_state) {
   if (!ctx) return fail(LBM_EINVAL, "context is NULL");
@@ -405,8 +534,7 @@ int lbm_create(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, void* r
   c->ready = false;
   c->t = 0;
   c->stream = (hipStream_t)stream;
-  const dim3 g = tile_grid(p->nx, p->ny);
-  c->nblocks = (int)(g.x * g.y);
+  c->nblocks = tiles_total<MomTile>(p->nx, p->ny);
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess) e = hipMalloc(&c->scratch, sizeof(double) * (3 * (size_t)c->nblocks + 3) + 64);
   if (e != hipSuccess) {
@@ -474,11 +602,13 @@ int lbm_step(lbm_ctx* ctx, int32_t n) {
   if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
   if (n == 0) return LBM_OK;
   if (int st = set_device(ctx)) return st;
-  const dim3 grid = tile_grid(ctx->p.nx, ctx->p.ny), block(TX, WY);
+  using S = StepTile;
+  const int ntx = tiles_x<S>(ctx->p.nx), ntiles = tiles_total<S>(ctx->p.nx, ctx->p.ny);
+  const dim3 block(S::TX, S::WY);
   for (int32_t s = 0; s < n; ++s) {
     const float* src = (const float*)ctx->buf[ctx->cur];
     float* dst = (float*)ctx->buf[ctx->cur ^ 1];
-    step_f32<<<grid, block, 0, ctx->stream>>>(src, dst, ctx->p.nx, ctx->p.ny, ctx->c);
+    step_f32<S><<<ntiles, block, 0, ctx->stream>>>(src, dst, ctx->p.nx, ctx->p.ny, ntx, ntiles, ctx->c);
     ctx->cur ^= 1;
   }
   HIP_OK(hipGetLastError());
@@ -489,9 +619,10 @@ int lbm_step(lbm_ctx* ctx, int32_t n) {
 int lbm_moments(lbm_ctx* ctx, float* rho, float* ux, float* uy, double totals[3]) {
   if (int st = check_ctx(ctx, true)) return st;
   if (int st = set_device(ctx)) return st;
-  const dim3 grid = tile_grid(ctx->p.nx, ctx->p.ny), block(TX, WY);
-  moments_f32<<<grid, block, 0, ctx->stream>>>((const float*)ctx->buf[ctx->cur], rho, ux, uy, ctx->scratch,
-                                               ctx->p.nx, ctx->p.ny, ctx->c);
+  using S = MomTile;
+  moments_f32<<<tiles_total<S>(ctx->p.nx, ctx->p.ny), dim3(S::TX, S::WY), 0, ctx->stream>>>(
+      (const float*)ctx->buf[ctx->cur], rho, ux, uy, ctx->scratch, ctx->p.nx, ctx->p.ny, tiles_x<S>(ctx->p.nx),
+      ctx->c);
   HIP_OK(hipGetLastError());
   if (!totals) return LBM_OK;
   double* tot = ctx->scratch + 3 * (size_t)ctx->nblocks;
