@@ -48,10 +48,17 @@ enum lbm_status {
   LBM_ESTATE = -5      /* call not valid in the current state              */
 };
 
+/* Storage of the post-collision populations in the A/B buffers.  The
+ * 2-byte storages keep S (f_i - f_ref,i) with f_ref the rest equilibrium at
+ * the reference density of the node the population streams to (that node's
+ * previous density in binary16, held in the rho_ref buffer), S = 2^12 for
+ * binary16 and 1 for bfloat16; arithmetic stays FP32.  The A/B buffer
+ * contents are internal; lbm_set_state / lbm_get_state exchange plain FP32
+ * post-streaming populations in the SoA layout above. */
 enum lbm_storage {
-  LBM_FP32 = 0, /* f_i stored as float                                   */
-  LBM_FP16 = 1, /* f_i stored as binary16 scaled deviations (see create)  */
-  LBM_BF16 = 2  /* f_i stored as bfloat16 scaled deviations               */
+  LBM_FP32 = 0, /* f_i stored as float (node mass conserved exactly)    */
+  LBM_FP16 = 1, /* scaled deviations in binary16                        */
+  LBM_BF16 = 2  /* scaled deviations in bfloat16                        */
 };
 
 /* The paper's problem statement: lattice, relaxation rates, varpi, the

@@ -116,7 +116,7 @@ __host__ __device__ __forceinline__ void forward_moments(const T* f, T* m) {
 // eight moving populations (FP64, exact), so the only change of the node's
 // mass is the one unbiased rounding of f_0; with the rounding of 1/9 it
 // would drift systematically.
-template <typename T>
+template <typename T, bool kExactMass = true>
 __host__ __device__ __forceinline__ void inverse_moments(const T* m, T* f, double mass) {
   const T w0 = m[0] * T(1.0 / 9.0), w1 = m[1] * T(1.0 / 36.0), w2 = m[2] * T(1.0 / 36.0);
   const T w3 = m[3] * T(1.0 / 6.0), w4 = m[4] * T(1.0 / 12.0);
@@ -132,10 +132,14 @@ __host__ __device__ __forceinline__ void inverse_moments(const T* m, T* f, doubl
   f[7] = (D + w8) - (P + Q);
   f[6] = (D - w8) + (Q - P);
   f[8] = (D - w8) - (Q - P);
-  double moving = (double)f[1];
+  if constexpr (kExactMass) {
+    double moving = (double)f[1];
 #pragma unroll
-  for (int i = 2; i < 9; ++i) moving += (double)f[i];
-  f[0] = (T)(mass - moving);
+    for (int i = 2; i < 9; ++i) moving += (double)f[i];
+    f[0] = (T)(mass - moving);
+  } else {
+    f[0] = m[0] - (((f[1] + f[3]) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8])));
+  }
 }
 
 // Node-local quantities at time t: velocity with the half-force correction
@@ -219,14 +223,14 @@ __host__ __device__ __forceinline__ void collide_moments(T* m, const NodeState<T
 
 // f-bar from pre-collision f at one node, given its exact mass
 // (density_exact(f)) and the stencil gradient g.
-template <typename T>
+template <typename T, bool kExactMass = true>
 __host__ __device__ __forceinline__ void collide_node(T* f, double mass, T gx, T gy, const Coef<T>& c) {
   T m[9];
   forward_moments(f, m);
   m[0] = (T)mass;
   const NodeState<T> s = node_state(m[0], m[3], m[5], gx, gy, c);
   collide_moments(m, s, gx, gy, c);
-  inverse_moments(m, f, mass);
+  inverse_moments<T, kExactMass>(m, f, mass);
 }
 
 // Equilibrium populations f^eq = M^-1 m^eq(rho, u, eta(rho)).
@@ -247,6 +251,24 @@ __host__ __device__ __forceinline__ void equilibrium_node(T rho, T ux, T uy, con
   m[7] = rho * (ux2 - uy2);
   m[8] = rho * ux * uy;
   inverse_moments(m, f, (double)rho);
+}
+
+// Reference populations of the 2-byte storages: the rest equilibrium
+// f^eq(rho~, eta_ref(rho~), u = 0) of a reference density rho~, per velocity
+// class (0 rest, 1 axis, 2 diagonal), as cubic polynomials in rho~ whose
+// coefficients the host fits once.  Stored values are S (f - f_ref).
+template <typename T>
+struct RefPoly {
+  T c[3][4];   // class value = ((c3 r + c2) r + c1) r + c0
+  T scale;     // S, a power of two
+  T inv_scale; // 1/S
+};
+
+__host__ __device__ __forceinline__ constexpr int velocity_class(int i) { return i == 0 ? 0 : (i <= 4 ? 1 : 2); }
+
+template <typename T>
+__host__ __device__ __forceinline__ T ref_value(const RefPoly<T>& q, int cls, T r) {
+  return ((q.c[cls][3] * r + q.c[cls][2]) * r + q.c[cls][1]) * r + q.c[cls][0];
 }
 
 }  // namespace lbm

@@ -5,10 +5,22 @@
 // fastest.  Two caller-owned buffers A and B alternate; the buffer that is
 // read by the next step holds the post-collision populations of the previous
 // step at their source node ("pull" streaming: f_i(x, t) = src_i(x - e_i)).
+//
+// Storages (one template parameter of every kernel):
+//   F32   f-bar stored as float;
+//   F16 / BF16  f-bar stored in two bytes as S (f-bar - f_ref), with f_ref the
+//         rest equilibrium at the reference density rho~ of the node the
+//         population streams to.  rho~ is that node's density of the previous
+//         step in binary16, kept in two planes that alternate like A and B.
+//         The encoder takes the neighbour densities from the LDS tile it
+//         already holds for the force stencil; the decoder reads its own rho~.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -38,98 +50,145 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 // ---------------------------------------------------------------------------
-// Index helpers
+// Velocity set (supplement Eq. 3) as compile-time tables
+// ---------------------------------------------------------------------------
+constexpr int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+// ---------------------------------------------------------------------------
+// Storage policies
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t f32_to_f16(float v) { return __half_as_ushort(__float2half_rn(v)); }
+__device__ __forceinline__ float f16_to_f32(uint16_t h) { return __half2float(__ushort_as_half(h)); }
+
+// binary32 -> bfloat16, round to nearest even (finite inputs).
+__device__ __forceinline__ uint16_t f32_to_bf16(float v) {
+  const uint32_t b = __float_as_uint(v);
+  return (uint16_t)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// The reference density rho~ of a node: its density rounded to binary16.
+__device__ __forceinline__ float ref_density(float rho) { return f16_to_f32(f32_to_f16(rho)); }
+
+struct StoreF32 {
+  using E = float;
+  static constexpr int ES = 4;
+  static constexpr bool kRef = false;
+};
+
+template <int KIND>
+struct Store16 {
+  using E = uint16_t;
+  static constexpr int ES = 2;
+  static constexpr bool kRef = true;
+  __device__ static float to_f32(uint16_t h) { return KIND == LBM_FP16 ? f16_to_f32(h) : bf16_to_f32(h); }
+  __device__ static uint16_t from_f32(float v) { return KIND == LBM_FP16 ? f32_to_f16(v) : f32_to_bf16(v); }
+};
+
+// ---------------------------------------------------------------------------
+// Addressing: per-plane base pointers (uniform) and 32-bit byte offsets
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int wrap(int i, int n) {
   i %= n;
   return i < 0 ? i + n : i;
 }
 
-// Pull the nine populations arriving at node (x, y): f_i(x) = src_i(x - e_i).
-// xm/xp, ym/yp are the periodic neighbours x-1/x+1, y-1/y+1.
-__device__ __forceinline__ void pull9(const float* __restrict__ src, size_t N, int nx, int x, int xm, int xp,
-                                      int y, int ym, int yp, float* f) {
-  const size_t r0 = (size_t)y * nx, rm = (size_t)ym * nx, rp = (size_t)yp * nx;
-  f[0] = src[r0 + x];
-  f[1] = src[1 * N + r0 + xm];
-  f[2] = src[2 * N + rm + x];
-  f[3] = src[3 * N + r0 + xp];
-  f[4] = src[4 * N + rp + x];
-  f[5] = src[5 * N + rm + xm];
-  f[6] = src[6 * N + rm + xp];
-  f[7] = src[7 * N + rp + xp];
-  f[8] = src[8 * N + rp + xm];
-}
-
-// The same pull with 32-bit byte offsets from per-plane base pointers (the
-// bases are uniform, so the loads use a scalar base plus one vector offset).
-// A node is addressed by its three row offsets (row * nx * 4 for rows y,
-// y-1, y+1) and three column offsets (4 x for x, x-1, x+1).
+// Row offsets (row * nx * ES) of rows y, y-1, y+1 and column offsets
+// (x * ES) of columns x, x-1, x+1 of a node, periodic.
+template <int ES>
 struct NodeAddr {
   unsigned r0, rm, rp, c0, cm, cp;
 };
 
-__device__ __forceinline__ NodeAddr node_addr(int x, int y, int nx, int ny) {
+template <int ES>
+__device__ __forceinline__ NodeAddr<ES> node_addr(int x, int y, int nx, int ny) {
   const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
   const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-  const unsigned rb = 4u * (unsigned)nx;
-  return {rb * (unsigned)y, rb * (unsigned)ym, rb * (unsigned)yp, 4u * (unsigned)x, 4u * (unsigned)xm,
-          4u * (unsigned)xp};
+  const unsigned rb = ES * (unsigned)nx;
+  return {rb * (unsigned)y, rb * (unsigned)ym, rb * (unsigned)yp, ES * (unsigned)x, ES * (unsigned)xm,
+          ES * (unsigned)xp};
 }
 
-__device__ __forceinline__ float ldb(const char* __restrict__ base, unsigned off) {
-  return *reinterpret_cast<const float*>(base + off);
+template <typename E>
+__device__ __forceinline__ E ldb(const char* __restrict__ base, unsigned off) {
+  return *reinterpret_cast<const E*>(base + off);
 }
 
+template <typename E>
 struct Planes {
   const char* p[9];
 };
 
-__device__ __forceinline__ Planes planes(const float* src, size_t N) {
-  Planes P;
+template <typename E>
+__device__ __forceinline__ Planes<E> planes(const void* src, size_t N) {
+  Planes<E> P;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) P.p[i] = reinterpret_cast<const char*>(src + (size_t)i * N);
+  for (int i = 0; i < 9; ++i) P.p[i] = reinterpret_cast<const char*>(reinterpret_cast<const E*>(src) + (size_t)i * N);
   return P;
 }
 
+template <typename E>
 struct OutPlanes {
   char* p[9];
 };
 
-__device__ __forceinline__ OutPlanes out_planes(float* dst, size_t N) {
-  OutPlanes P;
+template <typename E>
+__device__ __forceinline__ OutPlanes<E> out_planes(void* dst, size_t N) {
+  OutPlanes<E> P;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) P.p[i] = reinterpret_cast<char*>(dst + (size_t)i * N);
+  for (int i = 0; i < 9; ++i) P.p[i] = reinterpret_cast<char*>(reinterpret_cast<E*>(dst) + (size_t)i * N);
   return P;
 }
 
-__device__ __forceinline__ void pull9b(const Planes& P, const NodeAddr& a, float* f) {
-  f[0] = ldb(P.p[0], a.r0 + a.c0);
-  f[1] = ldb(P.p[1], a.r0 + a.cm);
-  f[2] = ldb(P.p[2], a.rm + a.c0);
-  f[3] = ldb(P.p[3], a.r0 + a.cp);
-  f[4] = ldb(P.p[4], a.rp + a.c0);
-  f[5] = ldb(P.p[5], a.rm + a.cm);
-  f[6] = ldb(P.p[6], a.rm + a.cp);
-  f[7] = ldb(P.p[7], a.rp + a.cp);
-  f[8] = ldb(P.p[8], a.rp + a.cm);
+// Raw stored values arriving at a node: raw_i = src_i(x - e_i).
+template <typename E>
+__device__ __forceinline__ void pull_raw(const Planes<E>& P, const NodeAddr<sizeof(E)>& a, E* r) {
+  r[0] = ldb<E>(P.p[0], a.r0 + a.c0);
+  r[1] = ldb<E>(P.p[1], a.r0 + a.cm);
+  r[2] = ldb<E>(P.p[2], a.rm + a.c0);
+  r[3] = ldb<E>(P.p[3], a.r0 + a.cp);
+  r[4] = ldb<E>(P.p[4], a.rp + a.c0);
+  r[5] = ldb<E>(P.p[5], a.rm + a.cm);
+  r[6] = ldb<E>(P.p[6], a.rm + a.cp);
+  r[7] = ldb<E>(P.p[7], a.rp + a.cp);
+  r[8] = ldb<E>(P.p[8], a.rp + a.cm);
 }
 
-// Tile order across the eight XCDs of the chip: workgroups are dealt to the
-// XCDs round-robin by dispatch index, so dispatch b runs on XCD b % 8.  Give
-// each XCD one contiguous run of tiles (in raster order) so that the tiles
-// whose halo lines overlap share that XCD's L2.  A bijection onto
-// [0, ntiles) for any ntiles.
-__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
-  const int q = ntiles >> 3, r = ntiles & 7, xcd = b & 7, local = b >> 3;
-  return xcd * q + (xcd < r ? xcd : r) + local;
+// Decode the raw values of a node into f_i (FP32).  rref is the node's
+// stored reference density (binary16 bits; ignored for F32).
+template <class St>
+__device__ __forceinline__ void decode(const typename St::E* r, uint16_t rref, const RefPoly<float>& q, float* f) {
+  if constexpr (St::kRef) {
+    const float rt = f16_to_f32(rref);
+    const float ref[3] = {ref_value(q, 0, rt), ref_value(q, 1, rt), ref_value(q, 2, rt)};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = ref[velocity_class(i)] + St::to_f32(r[i]) * q.inv_scale;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = r[i];
+  }
+}
+
+// Encode f-bar_i of one node given the reference densities of the nine
+// nodes its populations stream to (index i: x + e_i).
+template <class St>
+__device__ __forceinline__ void encode(const float* f, const float* rdest, const RefPoly<float>& q,
+                                       typename St::E* out) {
+  if constexpr (St::kRef) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) out[i] = St::from_f32((f[i] - ref_value(q, velocity_class(i), rdest[i])) * q.scale);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) out[i] = f[i];
+  }
 }
 
 // ---------------------------------------------------------------------------
-// Fused step: tile of TX x TY nodes per workgroup of TX x WY threads; each
-// thread owns NPT = TY/WY nodes of one column.  The tile plus a one-node
-// ring of densities is staged in LDS for the force stencil; ring nodes pull
-// their own populations (L2 hits: the neighbouring tiles run on the same XCD).
+// Tiles: TX x TY nodes per workgroup of TX x WY threads; each thread owns
+// NPT = TY/WY nodes of one column.  The tile plus a one-node ring of
+// densities is staged in LDS for the force stencil; ring nodes pull their
+// own populations (L2 hits: neighbouring tiles run on the same XCD).
 // ---------------------------------------------------------------------------
 template <int TX_, int TY_, int WY_>
 struct TileShape {
@@ -144,6 +203,17 @@ struct TileShape {
 #define LBM_STEP_TILE 128, 8, 4
 #endif
 using StepTile = TileShape<LBM_STEP_TILE>;
+using MomTile = TileShape<64, 16, 4>;
+
+// Tile order across the eight XCDs of the chip: workgroups are dealt to the
+// XCDs round-robin by dispatch index, so dispatch b runs on XCD b % 8.  Give
+// each XCD one contiguous run of tiles (in raster order) so that the tiles
+// whose halo lines overlap share that XCD's L2.  A bijection onto
+// [0, ntiles) for any ntiles.
+__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
+  const int q = ntiles >> 3, r = ntiles & 7, xcd = b & 7, local = b >> 3;
+  return xcd * q + (xcd < r ? xcd : r) + local;
+}
 
 // Coordinates (hx, hy) in the (TY+2) x LW density tile of ring slot t.
 template <class S>
@@ -159,111 +229,157 @@ __device__ __forceinline__ void ring_slot(int t, int& hx, int& hy) {
   }
 }
 
-// Populations of one tile held in registers: NPT own nodes per thread plus,
-// for the first NRING threads, one ring node.
-template <class S>
+// Stored values of one tile held in registers: NPT own nodes per thread and,
+// for the first NRING threads, one ring node; plus their reference densities.
+template <class S, class St>
 struct TileRegs {
-  float f[S::NPT][9];
-  float fr[9];
+  typename St::E raw[S::NPT][9];
+  typename St::E rraw[9];
+  uint16_t rref[S::NPT];
+  uint16_t rrref;
 };
 
 // Issue the loads of the tile at (x0, y0); ring loads first.
-template <class S>
-__device__ __forceinline__ void issue_tile(const Planes& P, int nx, int ny, int x0, int y0, TileRegs<S>& R) {
+template <class S, class St>
+__device__ __forceinline__ void issue_tile(const Planes<typename St::E>& P, const uint16_t* __restrict__ rho_ref,
+                                           int nx, int ny, int x0, int y0, TileRegs<S, St>& R) {
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * S::TX + tx;
   if (tid < S::NRING) {
     int hx, hy;
     ring_slot<S>(tid, hx, hy);
-    pull9b(P, node_addr(wrap(x0 + hx - 1, nx), wrap(y0 + hy - 1, ny), nx, ny), R.fr);
+    const int gx = wrap(x0 + hx - 1, nx), gy = wrap(y0 + hy - 1, ny);
+    pull_raw<typename St::E>(P, node_addr<St::ES>(gx, gy, nx, ny), R.rraw);
+    if constexpr (St::kRef) R.rrref = rho_ref[(size_t)gy * nx + gx];
   }
   const int xw = wrap(x0 + tx, nx);
 #pragma unroll
-  for (int k = 0; k < S::NPT; ++k) pull9b(P, node_addr(xw, wrap(y0 + ty + k * S::WY, ny), nx, ny), R.f[k]);
+  for (int k = 0; k < S::NPT; ++k) {
+    const int yw = wrap(y0 + ty + k * S::WY, ny);
+    pull_raw<typename St::E>(P, node_addr<St::ES>(xw, yw, nx, ny), R.raw[k]);
+    if constexpr (St::kRef) R.rref[k] = rho_ref[(size_t)yw * nx + xw];
+  }
 }
 
-// Densities of the tile and its ring into srho[(TY+2)][LW]; the exact
-// (FP64) masses of the own nodes are kept for the collision.
+// The three class values of the reference equilibrium at the reference
+// density of a tile node (2-byte storages), staged for the encoders of the
+// node's neighbours: sref[class * LDS + pos].
 template <class S>
-__device__ __forceinline__ void stage_density(const TileRegs<S>& R, double (&mass)[S::NPT], float* srho) {
+__device__ __forceinline__ void stage_ref(const RefPoly<float>& q, float rho, int pos, float* sref) {
+  const float rt = ref_density(rho);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) sref[c * S::LDS + pos] = ref_value(q, c, rt);
+}
+
+// Decode the tile, stage densities of the tile and its ring into
+// srho[(TY+2)][LW], keep the own nodes' populations and masses (exact FP64
+// sum for F32) in registers.
+template <class S, class St>
+__device__ __forceinline__ void stage_tile(const TileRegs<S, St>& R, const RefPoly<float>& q,
+                                           float (&f)[S::NPT][9], double (&mass)[S::NPT], float* srho,
+                                           float* sref) {
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * S::TX + tx;
 #pragma unroll
   for (int k = 0; k < S::NPT; ++k) {
-    mass[k] = density_exact(R.f[k]);
-    srho[(ty + k * S::WY + 1) * S::LW + tx + 1] = (float)mass[k];
+    decode<St>(R.raw[k], St::kRef ? R.rref[k] : 0, q, f[k]);
+    mass[k] = St::kRef ? (double)density(f[k]) : density_exact(f[k]);
+    const int pos = (ty + k * S::WY + 1) * S::LW + tx + 1;
+    srho[pos] = (float)mass[k];
+    if (St::kRef && sref) stage_ref<S>(q, (float)mass[k], pos, sref);
   }
   if (tid < S::NRING) {
     int hx, hy;
     ring_slot<S>(tid, hx, hy);
-    srho[hy * S::LW + hx] = density(R.fr);
+    float fr[9];
+    decode<St>(R.rraw, St::kRef ? R.rrref : 0, q, fr);
+    const float rho = St::kRef ? density(fr) : (float)density_exact(fr);
+    srho[hy * S::LW + hx] = rho;
+    if (St::kRef && sref) stage_ref<S>(q, rho, hy * S::LW + hx, sref);
   }
 }
 
+// The stencil neighbours of tile position (hx, hy), indexed like the
+// populations: nb[i] = rho(x + e_i) (nb[0] = rho(x)).
 template <class S>
-__device__ __forceinline__ void tile_gradient(const float* srho, int hx, int hy, float& gx, float& gy) {
+__device__ __forceinline__ void neighbours(const float* srho, int hx, int hy, float* nb) {
   const float* r = srho + hy * S::LW + hx;
-  stencil(r[1], r[S::LW], r[-1], r[-S::LW], r[S::LW + 1], r[S::LW - 1], r[-S::LW - 1], r[-S::LW + 1], gx, gy);
-}
-
-// Collide the own nodes of the tile at (x0, y0) and store f-bar at the node.
-template <class S>
-__device__ __forceinline__ void collide_tile(TileRegs<S>& R, const double (&mass)[S::NPT], const float* srho,
-                                             const OutPlanes& Q, int nx, int ny, int x0, int y0,
-                                             const Coef<float>& c) {
-  const int x = x0 + threadIdx.x;
-  if (x >= nx) return;
-  const unsigned rb = 4u * (unsigned)nx;
 #pragma unroll
-  for (int k = 0; k < S::NPT; ++k) {
-    const int ly = threadIdx.y + k * S::WY, y = y0 + ly;
-    if (y >= ny) break;
-    float gx, gy;
-    tile_gradient<S>(srho, threadIdx.x + 1, ly + 1, gx, gy);
-    collide_node(R.f[k], mass[k], gx, gy, c);
-    const unsigned o = rb * (unsigned)y + 4u * (unsigned)x;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(R.f[k][i], reinterpret_cast<float*>(Q.p[i] + o));
-  }
+  for (int i = 0; i < 9; ++i) nb[i] = r[kCy[i] * S::LW + kCx[i]];
 }
 
 // Step kernel: one tile per workgroup, tiles ordered across the XCDs by
 // xcd_tile so that neighbouring tiles (whose halo lines overlap) run on the
 // same XCD and share its L2.
-template <class S>
-__global__ __launch_bounds__(S::NTHREADS) void step_f32(const float* __restrict__ src, float* __restrict__ dst,
-                                                        int nx, int ny, int ntx, int ntiles, Coef<float> c) {
+template <class S, class St>
+__global__ __launch_bounds__(S::NTHREADS) void step_kernel(const void* __restrict__ src, void* __restrict__ dst,
+                                                           const uint16_t* __restrict__ ref_in,
+                                                           uint16_t* __restrict__ ref_out, int nx, int ny, int ntx,
+                                                           int ntiles, Coef<float> c, RefPoly<float> q) {
+  using E = typename St::E;
   __shared__ float srho[S::LDS];
+  __shared__ float sref[St::kRef ? 3 * S::LDS : 1];
   const size_t N = (size_t)nx * ny;
   const int tile = xcd_tile(blockIdx.x, ntiles);
   const int x0 = (tile % ntx) * S::TX, y0 = (tile / ntx) * S::TY;
-  TileRegs<S> R;
+  float f[S::NPT][9];
   double mass[S::NPT];
-  issue_tile<S>(planes(src, N), nx, ny, x0, y0, R);
-  stage_density<S>(R, mass, srho);
+  {
+    TileRegs<S, St> R;
+    issue_tile<S, St>(planes<E>(src, N), ref_in, nx, ny, x0, y0, R);
+    stage_tile<S, St>(R, q, f, mass, srho, St::kRef ? sref : nullptr);
+  }
   __syncthreads();
-  collide_tile<S>(R, mass, srho, out_planes(dst, N), nx, ny, x0, y0, c);
+  const int x = x0 + threadIdx.x;
+  if (x >= nx) return;
+  const OutPlanes<E> Q = out_planes<E>(dst, N);
+  const unsigned rb = St::ES * (unsigned)nx;
+#pragma unroll
+  for (int k = 0; k < S::NPT; ++k) {
+    const int ly = threadIdx.y + k * S::WY, y = y0 + ly;
+    if (y >= ny) break;
+    float nb[9];
+    neighbours<S>(srho, threadIdx.x + 1, ly + 1, nb);
+    float gx, gy;
+    stencil(nb[1], nb[2], nb[3], nb[4], nb[5], nb[6], nb[7], nb[8], gx, gy);
+    collide_node<float, !St::kRef>(f[k], mass[k], gx, gy, c);
+    E out[9];
+    if constexpr (St::kRef) {
+      // f-bar_i streams to x + e_i: encode it against that node's reference
+      const int pos = (ly + 1) * S::LW + threadIdx.x + 1;
+#pragma unroll
+      for (int i = 0; i < 9; ++i)
+        out[i] = St::from_f32((f[k][i] - sref[velocity_class(i) * S::LDS + pos + kCy[i] * S::LW + kCx[i]]) *
+                              q.scale);
+      ref_out[(size_t)y * nx + x] = f32_to_f16(nb[0]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) out[i] = f[k][i];
+    }
+    const unsigned o = rb * (unsigned)y + St::ES * (unsigned)x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(out[i], reinterpret_cast<E*>(Q.p[i] + o));
+  }
 }
 
 // Moments: rho and u of main Eq. 5 plus per-workgroup FP64 partial sums of
 // mass and lattice momentum (reduced in a fixed order).
-using MomTile = TileShape<64, 16, 4>;
-
-__global__ __launch_bounds__(MomTile::NTHREADS) void moments_f32(const float* __restrict__ src,
-                                                                 float* __restrict__ rho_out,
-                                                                 float* __restrict__ ux_out,
-                                                                 float* __restrict__ uy_out,
-                                                                 double* __restrict__ partials, int nx, int ny,
-                                                                 int ntx, Coef<float> c) {
+template <class St>
+__global__ __launch_bounds__(MomTile::NTHREADS) void moments_kernel(
+    const void* __restrict__ src, const uint16_t* __restrict__ ref_in, float* __restrict__ rho_out,
+    float* __restrict__ ux_out, float* __restrict__ uy_out, double* __restrict__ partials, int nx, int ny, int ntx,
+    Coef<float> c, RefPoly<float> q) {
   using S = MomTile;
   __shared__ float srho[S::LDS];
   __shared__ double sred[3][S::NTHREADS];
   const size_t N = (size_t)nx * ny;
   const int x0 = (blockIdx.x % ntx) * S::TX, y0 = (blockIdx.x / ntx) * S::TY;
-  TileRegs<S> R;
+  float f[S::NPT][9];
   double mass[S::NPT];
-  issue_tile<S>(planes(src, N), nx, ny, x0, y0, R);
-  stage_density<S>(R, mass, srho);
+  {
+    TileRegs<S, St> R;
+    issue_tile<S, St>(planes<typename St::E>(src, N), ref_in, nx, ny, x0, y0, R);
+    stage_tile<S, St>(R, q, f, mass, srho, nullptr);
+  }
   __syncthreads();
-  auto& f = R.f;
   const int x = x0 + threadIdx.x;
   double sm = 0.0, sx = 0.0, sy = 0.0;
 #pragma unroll
@@ -272,8 +388,10 @@ __global__ __launch_bounds__(MomTile::NTHREADS) void moments_f32(const float* __
     if (x >= nx || y >= ny) continue;
     float m[9];
     forward_moments(f[k], m);
-    float gx, gy;
-    tile_gradient<S>(srho, threadIdx.x + 1, ly + 1, gx, gy);
+    m[0] = (float)mass[k];
+    float nb[9], gx, gy;
+    neighbours<S>(srho, threadIdx.x + 1, ly + 1, nb);
+    stencil(nb[1], nb[2], nb[3], nb[4], nb[5], nb[6], nb[7], nb[8], gx, gy);
     const NodeState<float> s = node_state(m[0], m[3], m[5], gx, gy, c);
     const size_t o = (size_t)y * nx + x;
     if (rho_out) rho_out[o] = m[0];
@@ -316,68 +434,79 @@ __global__ __launch_bounds__(RED) void finish_sums(const double* __restrict__ pa
   if (threadIdx.x < 3) out[threadIdx.x] = s[threadIdx.x][0];
 }
 
-// Initial state: node x computes f^eq(rho0, u0, eta(rho0)) and stores f_i at
-// x - e_i, so that the first pull returns f^eq at x.  Raises *flag on a
+// Store the post-streaming populations f of node (x, y) into the pull
+// layout: f_i goes to slot (i, x - e_i), encoded against the reference
+// density of (x, y), which is also written (2-byte storages).
+template <class St>
+__device__ __forceinline__ void put_node(int x, int y, int nx, int ny, const float* f, const RefPoly<float>& q,
+                                         void* dst, uint16_t* ref_out) {
+  using E = typename St::E;
+  const size_t N = (size_t)nx * ny;
+  float rd[9];
+  if constexpr (St::kRef) {
+    const float r = ref_density(density(f));
+    ref_out[(size_t)y * nx + x] = f32_to_f16(r);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) rd[i] = r;
+  }
+  E out[9];
+  encode<St>(f, rd, q, out);
+  E* d = reinterpret_cast<E*>(dst);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int xs = wrap(x - kCx[i], nx), ys = wrap(y - kCy[i], ny);
+    d[(size_t)i * N + (size_t)ys * nx + xs] = out[i];
+  }
+}
+
+// Initial state: f^eq(rho0, u0, eta(rho0)) at every node.  Raises *flag on a
 // density outside (0, 4/b) or a non-finite input.
 constexpr int BLK = 256;
-__global__ __launch_bounds__(BLK) void init_f32(const float* __restrict__ rho0, const float* __restrict__ ux0,
-                                                const float* __restrict__ uy0, float* __restrict__ dst, int nx,
-                                                int ny, Coef<float> c, int* flag) {
+template <class St>
+__global__ __launch_bounds__(BLK) void init_kernel(const float* __restrict__ rho0, const float* __restrict__ ux0,
+                                                   const float* __restrict__ uy0, void* __restrict__ dst,
+                                                   uint16_t* __restrict__ ref_out, int nx, int ny, Coef<float> c,
+                                                   RefPoly<float> q, int* flag) {
   const size_t N = (size_t)nx * ny;
   const size_t o = (size_t)blockIdx.x * BLK + threadIdx.x;
   if (o >= N) return;
-  const int x = (int)(o % nx), y = (int)(o / nx);
   const float r = rho0[o], ux = ux0 ? ux0[o] : 0.0f, uy = uy0 ? uy0[o] : 0.0f;
   if (!(r > 0.0f && c.b4 * r < 1.0f) || !isfinite(ux) || !isfinite(uy)) atomicOr(flag, 1);
   float f[9];
   equilibrium_node(r, ux, uy, c, f);
-  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-  const size_t r0 = (size_t)y * nx, rm = (size_t)ym * nx, rp = (size_t)yp * nx;
-  // population i stored at x - e_i
-  dst[r0 + x] = f[0];
-  dst[1 * N + r0 + xm] = f[1];
-  dst[2 * N + rm + x] = f[2];
-  dst[3 * N + r0 + xp] = f[3];
-  dst[4 * N + rp + x] = f[4];
-  dst[5 * N + rm + xm] = f[5];
-  dst[6 * N + rm + xp] = f[6];
-  dst[7 * N + rp + xp] = f[7];
-  dst[8 * N + rp + xm] = f[8];
+  put_node<St>((int)(o % nx), (int)(o / nx), nx, ny, f, q, dst, ref_out);
 }
 
-// Load a post-streaming state (un-stream it into the pull source layout).
-__global__ __launch_bounds__(BLK) void set_state_f32(const float* __restrict__ fin, float* __restrict__ dst, int nx,
-                                                     int ny) {
+// Load a post-streaming state.
+template <class St>
+__global__ __launch_bounds__(BLK) void set_state_kernel(const float* __restrict__ fin, void* __restrict__ dst,
+                                                        uint16_t* __restrict__ ref_out, int nx, int ny,
+                                                        RefPoly<float> q) {
   const size_t N = (size_t)nx * ny;
   const size_t o = (size_t)blockIdx.x * BLK + threadIdx.x;
   if (o >= N) return;
-  const int x = (int)(o % nx), y = (int)(o / nx);
-  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-  const size_t r0 = (size_t)y * nx, rm = (size_t)ym * nx, rp = (size_t)yp * nx;
-  dst[r0 + x] = fin[o];
-  dst[1 * N + r0 + xm] = fin[1 * N + o];
-  dst[2 * N + rm + x] = fin[2 * N + o];
-  dst[3 * N + r0 + xp] = fin[3 * N + o];
-  dst[4 * N + rp + x] = fin[4 * N + o];
-  dst[5 * N + rm + xm] = fin[5 * N + o];
-  dst[6 * N + rm + xp] = fin[6 * N + o];
-  dst[7 * N + rp + xp] = fin[7 * N + o];
-  dst[8 * N + rp + xm] = fin[8 * N + o];
-}
-
-__global__ __launch_bounds__(BLK) void get_state_f32(const float* __restrict__ src, float* __restrict__ fout, int nx,
-                                                     int ny) {
-  const size_t N = (size_t)nx * ny;
-  const size_t o = (size_t)blockIdx.x * BLK + threadIdx.x;
-  if (o >= N) return;
-  const int x = (int)(o % nx), y = (int)(o / nx);
-  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
   float f[9];
-  pull9(src, N, nx, x, xm, xp, y, ym, yp, f);
-  for (int i = 0; i < 9; ++i) fout[i * N + o] = f[i];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) f[i] = fin[(size_t)i * N + o];
+  put_node<St>((int)(o % nx), (int)(o / nx), nx, ny, f, q, dst, ref_out);
+}
+
+// Export the post-streaming state f(t).
+template <class St>
+__global__ __launch_bounds__(BLK) void get_state_kernel(const void* __restrict__ src,
+                                                        const uint16_t* __restrict__ ref_in, float* __restrict__ fout,
+                                                        int nx, int ny, RefPoly<float> q) {
+  using E = typename St::E;
+  const size_t N = (size_t)nx * ny;
+  const size_t o = (size_t)blockIdx.x * BLK + threadIdx.x;
+  if (o >= N) return;
+  const int x = (int)(o % nx), y = (int)(o / nx);
+  E raw[9];
+  pull_raw<E>(planes<E>(src, N), node_addr<St::ES>(x, y, nx, ny), raw);
+  float f[9];
+  decode<St>(raw, St::kRef ? ref_in[o] : 0, q, f);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) fout[(size_t)i * N + o] = f[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -440,6 +569,60 @@ Coef<float> make_coef(const lbm_derived& d, double varpi, double a, double b) {
   return f;
 }
 
+// Reference populations of the 2-byte storages.  eta(rho) of the model
+// (p_LBE = (rho + eta)/3 with the CS pressure) is replaced by its cubic
+// least-squares fit on [0, 1.25 rho_l]; any smooth fit keeps encoder and
+// decoder consistent, a closer one keeps the stored deviations small.  The
+// class values are those of the rest equilibrium:
+//   rest  (16 rho + (4 beta2 - 8) eta)/36,  axis rho/9 - (1 + beta2) eta/18,
+//   diag  rho/36 + (4 + beta2) eta/36.
+RefPoly<float> make_refpoly(const lbm_derived& d, double a, double b, int storage) {
+  const int n = 257;
+  const double rmax = 1.25 * d.rho_l;
+  double A[4][4] = {}, B[4] = {};
+  for (int j = 0; j < n; ++j) {
+    const double r = rmax * 0.5 * (1.0 - std::cos(M_PI * j / (n - 1)));
+    const double v = 0.25 * b * r, w = 1.0 - v;
+    const double z = (1.0 + v + v * v - v * v * v) / (w * w * w);
+    const double p = d.kp * (r * d.rt * z - a * r * r) + 0.5 * d.g2 * r * r;
+    const double eta = 3.0 * p - r;
+    const double bas[4] = {1.0, r, r * r, r * r * r};
+    for (int u = 0; u < 4; ++u) {
+      B[u] += bas[u] * eta;
+      for (int v2 = 0; v2 < 4; ++v2) A[u][v2] += bas[u] * bas[v2];
+    }
+  }
+  // Gaussian elimination with partial pivoting (4x4)
+  double e[4];
+  for (int col = 0; col < 4; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < 4; ++r)
+      if (std::fabs(A[r][col]) > std::fabs(A[piv][col])) piv = r;
+    for (int u = 0; u < 4; ++u) std::swap(A[col][u], A[piv][u]);
+    std::swap(B[col], B[piv]);
+    for (int r = col + 1; r < 4; ++r) {
+      const double fac = A[r][col] / A[col][col];
+      for (int u = col; u < 4; ++u) A[r][u] -= fac * A[col][u];
+      B[r] -= fac * B[col];
+    }
+  }
+  for (int r = 3; r >= 0; --r) {
+    double s = B[r];
+    for (int u = r + 1; u < 4; ++u) s -= A[r][u] * e[u];
+    e[r] = s / A[r][r];
+  }
+  const double be = d.beta2;
+  const double lin[3] = {16.0 / 36.0, 1.0 / 9.0, 1.0 / 36.0};  // coefficient of rho
+  const double eta_c[3] = {(4.0 * be - 8.0) / 36.0, -(1.0 + be) / 18.0, (4.0 + be) / 36.0};
+  RefPoly<float> q{};
+  for (int cls = 0; cls < 3; ++cls)
+    for (int u = 0; u < 4; ++u) q.c[cls][u] = (float)(eta_c[cls] * e[u] + (u == 1 ? lin[cls] : 0.0));
+  const double S = storage == LBM_FP16 ? 4096.0 : 1.0;
+  q.scale = (float)S;
+  q.inv_scale = (float)(1.0 / S);
+  return q;
+}
+
 }  // namespace
 }  // namespace lbm
 
@@ -449,15 +632,16 @@ struct lbm_ctx {
   lbm_params p;
   lbm_derived d;
   Coef<float> c;
+  RefPoly<float> q;
   void* buf[2];
-  void* rho_ref;
-  int cur;        // buffer holding the pull source of the next step
-  bool ready;     // state initialised
+  uint16_t* ref[2];  // reference-density planes (2-byte storages)
+  int cur;           // buffer holding the pull source of the next step
+  bool ready;        // state initialised
   int64_t t;
   hipStream_t stream;
   int device;
-  int nblocks;    // workgroups of the moments tile grid
-  double* scratch;  // nblocks*3 partials, then 3 totals
+  int nblocks;       // workgroups of the moments tile grid
+  double* scratch;   // nblocks*3 partials, then 3 totals
   int* flag;
 };
 
@@ -482,6 +666,16 @@ int set_device(const lbm_ctx* ctx) {
 }
 
 size_t grid1(size_t n) { return (n + BLK - 1) / BLK; }
+
+// Call fn with the storage policy of the context.
+template <class Fn>
+int with_storage(const lbm_ctx* ctx, Fn&& fn) {
+  switch (ctx->p.storage) {
+    case LBM_FP32: return fn(StoreF32{});
+    case LBM_FP16: return fn(Store16<LBM_FP16>{});
+    default: return fn(Store16<LBM_BF16>{});
+  }
+}
 
 }  // namespace
 
@@ -520,16 +714,20 @@ int lbm_create(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, void* r
   lbm_derived d;
   int st = lbm::derive(p, &d, g_err, sizeof g_err);
   if (st) return st;
-  if (p->storage != LBM_FP32) return fail(LBM_EINVAL, "this build supports LBM_FP32 storage only");
   if (!f_a || !f_b || f_a == f_b) return fail(LBM_EINVAL, "f_a and f_b must be two distinct device buffers");
+  if (p->storage != LBM_FP32 && !rho_ref)
+    return fail(LBM_EINVAL, "the 2-byte storages need the reference-density buffer rho_ref");
   lbm_ctx* c = new (std::nothrow) lbm_ctx{};
   if (!c) return fail(LBM_EINVAL, "out of host memory");
   c->p = *p;
   c->d = d;
   c->c = make_coef(d, p->varpi, p->a, p->b);
+  c->q = make_refpoly(d, p->a, p->b, p->storage);
   c->buf[0] = f_a;
   c->buf[1] = f_b;
-  c->rho_ref = rho_ref;
+  const size_t N = (size_t)p->nx * p->ny;
+  c->ref[0] = p->storage == LBM_FP32 ? nullptr : reinterpret_cast<uint16_t*>(rho_ref);
+  c->ref[1] = p->storage == LBM_FP32 ? nullptr : reinterpret_cast<uint16_t*>(rho_ref) + N;
   c->cur = 0;
   c->ready = false;
   c->t = 0;
@@ -558,9 +756,14 @@ int lbm_init(lbm_ctx* ctx, const float* rho0, const float* ux0, const float* uy0
   if (int st = set_device(ctx)) return st;
   const size_t N = (size_t)ctx->p.nx * ctx->p.ny;
   HIP_OK(hipMemsetAsync(ctx->flag, 0, sizeof(int), ctx->stream));
-  float* dst = (float*)ctx->buf[0];
-  init_f32<<<grid1(N), BLK, 0, ctx->stream>>>(rho0, ux0, uy0, dst, ctx->p.nx, ctx->p.ny, ctx->c, ctx->flag);
-  HIP_OK(hipGetLastError());
+  int st = with_storage(ctx, [&](auto store) -> int {
+    using St = decltype(store);
+    init_kernel<St><<<grid1(N), BLK, 0, ctx->stream>>>(rho0, ux0, uy0, ctx->buf[0], ctx->ref[0], ctx->p.nx,
+                                                        ctx->p.ny, ctx->c, ctx->q, ctx->flag);
+    HIP_OK(hipGetLastError());
+    return LBM_OK;
+  });
+  if (st) return st;
   int flag = 0;
   HIP_OK(hipMemcpyAsync(&flag, ctx->flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   HIP_OK(hipStreamSynchronize(ctx->stream));
@@ -579,8 +782,14 @@ int lbm_set_state(lbm_ctx* ctx, const float* f) {
   if (!f) return fail(LBM_EINVAL, "f is NULL");
   if (int st = set_device(ctx)) return st;
   const size_t N = (size_t)ctx->p.nx * ctx->p.ny;
-  set_state_f32<<<grid1(N), BLK, 0, ctx->stream>>>(f, (float*)ctx->buf[0], ctx->p.nx, ctx->p.ny);
-  HIP_OK(hipGetLastError());
+  int st = with_storage(ctx, [&](auto store) -> int {
+    using St = decltype(store);
+    set_state_kernel<St><<<grid1(N), BLK, 0, ctx->stream>>>(f, ctx->buf[0], ctx->ref[0], ctx->p.nx, ctx->p.ny,
+                                                             ctx->q);
+    HIP_OK(hipGetLastError());
+    return LBM_OK;
+  });
+  if (st) return st;
   ctx->cur = 0;
   ctx->t = 0;
   ctx->ready = true;
@@ -592,9 +801,13 @@ int lbm_get_state(lbm_ctx* ctx, float* f) {
   if (!f) return fail(LBM_EINVAL, "f is NULL");
   if (int st = set_device(ctx)) return st;
   const size_t N = (size_t)ctx->p.nx * ctx->p.ny;
-  get_state_f32<<<grid1(N), BLK, 0, ctx->stream>>>((const float*)ctx->buf[ctx->cur], f, ctx->p.nx, ctx->p.ny);
-  HIP_OK(hipGetLastError());
-  return LBM_OK;
+  return with_storage(ctx, [&](auto store) -> int {
+    using St = decltype(store);
+    get_state_kernel<St><<<grid1(N), BLK, 0, ctx->stream>>>(ctx->buf[ctx->cur], ctx->ref[ctx->cur], f, ctx->p.nx,
+                                                             ctx->p.ny, ctx->q);
+    HIP_OK(hipGetLastError());
+    return LBM_OK;
+  });
 }
 
 int lbm_step(lbm_ctx* ctx, int32_t n) {
@@ -605,13 +818,18 @@ int lbm_step(lbm_ctx* ctx, int32_t n) {
   using S = StepTile;
   const int ntx = tiles_x<S>(ctx->p.nx), ntiles = tiles_total<S>(ctx->p.nx, ctx->p.ny);
   const dim3 block(S::TX, S::WY);
-  for (int32_t s = 0; s < n; ++s) {
-    const float* src = (const float*)ctx->buf[ctx->cur];
-    float* dst = (float*)ctx->buf[ctx->cur ^ 1];
-    step_f32<S><<<ntiles, block, 0, ctx->stream>>>(src, dst, ctx->p.nx, ctx->p.ny, ntx, ntiles, ctx->c);
-    ctx->cur ^= 1;
-  }
-  HIP_OK(hipGetLastError());
+  int st = with_storage(ctx, [&](auto store) -> int {
+    using St = decltype(store);
+    for (int32_t s = 0; s < n; ++s) {
+      const int a = ctx->cur, b = ctx->cur ^ 1;
+      step_kernel<S, St><<<ntiles, block, 0, ctx->stream>>>(ctx->buf[a], ctx->buf[b], ctx->ref[a], ctx->ref[b],
+                                                            ctx->p.nx, ctx->p.ny, ntx, ntiles, ctx->c, ctx->q);
+      ctx->cur = b;
+    }
+    HIP_OK(hipGetLastError());
+    return LBM_OK;
+  });
+  if (st) return st;
   ctx->t += n;
   return LBM_OK;
 }
@@ -620,10 +838,15 @@ int lbm_moments(lbm_ctx* ctx, float* rho, float* ux, float* uy, double totals[3]
   if (int st = check_ctx(ctx, true)) return st;
   if (int st = set_device(ctx)) return st;
   using S = MomTile;
-  moments_f32<<<tiles_total<S>(ctx->p.nx, ctx->p.ny), dim3(S::TX, S::WY), 0, ctx->stream>>>(
-      (const float*)ctx->buf[ctx->cur], rho, ux, uy, ctx->scratch, ctx->p.nx, ctx->p.ny, tiles_x<S>(ctx->p.nx),
-      ctx->c);
-  HIP_OK(hipGetLastError());
+  int st = with_storage(ctx, [&](auto store) -> int {
+    using St = decltype(store);
+    moments_kernel<St><<<tiles_total<S>(ctx->p.nx, ctx->p.ny), dim3(S::TX, S::WY), 0, ctx->stream>>>(
+        ctx->buf[ctx->cur], ctx->ref[ctx->cur], rho, ux, uy, ctx->scratch, ctx->p.nx, ctx->p.ny,
+        tiles_x<S>(ctx->p.nx), ctx->c, ctx->q);
+    HIP_OK(hipGetLastError());
+    return LBM_OK;
+  });
+  if (st) return st;
   if (!totals) return LBM_OK;
   double* tot = ctx->scratch + 3 * (size_t)ctx->nblocks;
   finish_sums<<<1, RED, 0, ctx->stream>>>(ctx->scratch, ctx->nblocks, tot);

@@ -1,0 +1,114 @@
+"""Two-byte storage of f as scaled deviations from a local reference
+equilibrium (FP16 and BF16), against the FP64 oracle and the Maxwell
+construction.  The storage rounds every population each step, so the bound
+is a tolerance derived from the 11-bit (FP16) / 8-bit (BF16) significand,
+not the FP32 bound; the coexistence-density error must stay <= 1e-3 of
+rho_l."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1809_02390_amd as pkg
+import workloads as wl
+from oracle import hostmap as hm
+from oracle import lbm, measure
+from tests._gpu_helpers import lattice, oracle_init, params_pair, sampled_oracle, device_samples
+
+pytestmark = pytest.mark.gpu
+STORAGES = ["fp16", "bf16"]
+# max |Delta rho| / rho_l after 100 steps of the 96^2 droplet (T_r = 0.7):
+# one rounding of a deviation of ~1e-3 rho per step is ~2^-12 (FP16) or
+# ~2^-9 (BF16) of it; the bounds leave a factor ~5 over what the run shows.
+STEP_TOL = {"fp16": 1e-4, "bf16": 1e-3}
+
+
+def droplet(n=96, tr=0.7):
+    _, co = params_pair(n, n, tr=tr)
+    return co, wl.droplets(n, n, co.rho_g, co.rho_l, co.width, [(n / 2, n / 2)], [n / 4])
+
+
+@pytest.mark.parametrize("storage", STORAGES)
+def test_roundtrip_of_a_state(storage):
+    """set_state then get_state returns every population to the storage's
+    precision relative to its deviation from the reference."""
+    co, rho = droplet(48)
+    rng = np.random.default_rng(1)
+    ux, uy = rng.uniform(-0.05, 0.05, (2, 48, 48))
+    f = oracle_init(co, rho, ux, uy)
+    lat = pkg.Lattice(48, 48, tr=0.7, storage=storage).set_state(torch.tensor(f, dtype=torch.float32, device="cuda"))
+    g = lat.state().double().cpu().numpy()
+    eq0 = lbm.equilibrium(f.sum(0), co)  # the deviation the storage rounds is at most |f - f_eq(rho, 0)| + |ref fit|
+    dev = np.abs(f - eq0).max()
+    rel = {"fp16": 2.0 ** -11, "bf16": 2.0 ** -8}[storage]
+    assert np.abs(g - f).max() <= rel * (dev + 0.02 * co.rho_l) + 1e-7
+
+
+@pytest.mark.parametrize("storage", STORAGES)
+def test_step_parity_within_storage_precision(storage):
+    co, rho = droplet()
+    lat = lattice(96, 96, rho, tr=0.7, storage=storage)
+    lat.step(100)
+    f = lbm.run(oracle_init(co, rho), co, 100)
+    err = np.abs(lat.state().double().cpu().numpy().sum(0) - f.sum(0)).max() / co.rho_l
+    assert err <= STEP_TOL[storage], err
+
+
+@pytest.mark.parametrize("storage", STORAGES)
+def test_ragged_lattice_runs_and_matches_fp32(storage):
+    """Ragged tiles: the 2-byte run stays within storage precision of FP32."""
+    _, co = params_pair(70, 37, tr=0.8)
+    rho = wl.droplets(70, 37, co.rho_g, co.rho_l, co.width, [(30, 20)], [11.0])
+    a = lattice(70, 37, rho, tr=0.8, storage=storage)
+    b = lattice(70, 37, rho, tr=0.8)
+    a.step(50)
+    b.step(50)
+    err = (a.moments()[0] - b.moments()[0]).abs().max().item() / co.rho_l
+    assert err <= STEP_TOL[storage], err
+
+
+@pytest.mark.parametrize("storage", ["fp32"] + STORAGES)
+def test_coexistence_error(storage):
+    """Flat interface relaxed for 20000 steps at T_r = 0.7: coexistence
+    densities within 1e-3 of rho_l of the Maxwell values, and the 2-byte
+    result within 1e-4 of rho_l of the FP32 one."""
+    _, co = params_pair(4, 128, tr=0.7, width=10.0)
+    rho = wl.flat_slab(4, 128, co.rho_g, co.rho_l, co.width / wl.TANH_WIDTH_FACTOR)
+
+    def run(st):
+        lat = lattice(4, 128, rho, tr=0.7, width=10.0, storage=st)
+        lat.step(20000)
+        return measure.bulk_densities(lat.moments()[0].double().cpu().numpy()[:, 1])
+
+    g, l = run(storage)
+    assert abs(l - co.rho_l) / co.rho_l <= 1e-3
+    assert abs(g - co.rho_g) / co.rho_l <= 1e-3
+    if storage != "fp32":
+        g32, l32 = run("fp32")
+        assert abs(l - l32) / co.rho_l <= 1e-4 and abs(g - g32) / co.rho_l <= 1e-4
+
+
+@pytest.mark.parametrize("storage", STORAGES)
+def test_mass_drift(storage):
+    """Storage rounding is unbiased: total mass moves by far less than the
+    per-step rounding would allow if it were systematic."""
+    co, rho = droplet()
+    lat = lattice(96, 96, rho, tr=0.7, storage=storage)
+    m0 = lat.moments(fields=False)[0]
+    lat.step(2000)
+    m1 = lat.moments(fields=False)[0]
+    assert abs(m1 - m0) / m0 < {"fp16": 1e-5, "bf16": 1e-4}[storage]
+
+
+@pytest.mark.parametrize("storage", STORAGES)
+def test_sampled_parity_spinodal_4096(storage):
+    """Full 4096^2 spinodal workload in the launch configuration the
+    benchmark times: sampled nodes after 20 steps against oracle crops."""
+    n, steps = 4096, 20
+    _, co = params_pair(n, n, tr=0.7, width=10.0)
+    rho = wl.spinodal(co, n=n)
+    lat = lattice(n, n, rho, tr=0.7, width=10.0, storage=storage)
+    lat.step(steps)
+    pts = [(0, 0), (n - 1, n - 1), (63, 15), (2047, 2048), (1234, 3071)]
+    ref = sampled_oracle(co, rho, pts, steps)
+    got = device_samples(lat.state(), pts)
+    assert np.abs(got - ref).max() / co.rho_l <= STEP_TOL[storage]
