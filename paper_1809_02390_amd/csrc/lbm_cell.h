@@ -271,4 +271,243 @@ __host__ __device__ __forceinline__ T ref_value(const RefPoly<T>& q, int cls, T 
   return ((q.c[cls][3] * r + q.c[cls][2]) * r + q.c[cls][1]) * r + q.c[cls][0];
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint of the per-node collision
+// ---------------------------------------------------------------------------
+// M^T a by the same add/subtract tree as inverse_moments (M^-1 = M^T D).
+template <typename T>
+__host__ __device__ __forceinline__ void transpose_moments(const T* a, T* f) {
+  const T A = a[0] - a[1] - T(2) * a[2], X = a[3] - T(2) * a[4], Y = a[5] - T(2) * a[6];
+  f[0] = a[0] + T(4) * (a[2] - a[1]);
+  f[1] = (A + a[7]) + X;
+  f[3] = (A + a[7]) - X;
+  f[2] = (A - a[7]) + Y;
+  f[4] = (A - a[7]) - Y;
+  const T D = a[0] + T(2) * a[1] + a[2], P = a[3] + a[4], Q = a[5] + a[6];
+  f[5] = (D + a[8]) + (P + Q);
+  f[7] = (D + a[8]) - (P + Q);
+  f[6] = (D - a[8]) + (Q - P);
+  f[8] = (D - a[8]) - (Q - P);
+}
+
+// Reverse-mode derivative of collide_node.  Given the pre-collision
+// populations f, the stencil gradient g and lam = dL/d f-bar, returns
+// lam_f = dL/d f (at fixed g), a_g = dL/d g, and adds dL/d(G'^2, K', R T)
+// to a_th.  The forward quantities are recomputed here; the sweep visits the
+// assignments of collide_node / collide_moments / node_state / eos in
+// reverse order.
+template <typename T>
+__host__ __device__ __forceinline__ void collide_node_vjp(const T* f, T gx, T gy, const Coef<T>& c, const T* lam,
+                                                          T* lam_f, T& a_gx, T& a_gy, T* a_th) {
+  // ---- forward recomputation --------------------------------------------
+  T m[9];
+  forward_moments(f, m);
+  const T rho = m[0];
+  const T Fx = c.g2 * rho * gx, Fy = c.g2 * rho * gy;
+  const T inv = recip(rho);
+  const T ux = (m[3] + T(0.5) * Fx) * inv, uy = (m[5] + T(0.5) * Fy) * inv;
+  const T v = c.b4 * rho;
+  const T iw = recip(T(1) - v);
+  const T iw3 = iw * iw * iw;
+  const T z = (T(1) + v * (T(1) + v * (T(1) - v))) * iw3;
+  const T dz = (T(1) + v * (T(4) + v * (T(4) + v * (v - T(4))))) * (iw3 * iw);
+  const T p = rho * (c.kprt * z + c.e_rho * rho);
+  const T dp = c.kprt * dz + c.de_rho * rho;
+  const T eta = T(3) * p - rho;
+  const T ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy, u2 = ux2 + uy2, dxy = ux2 - uy2;
+  const T meq1 = T(2) * (eta - rho) + T(3) * rho * u2;
+  const T meq2 = c.alpha2 * rho + c.beta2 * eta + rho * (T(9) * ux2 * uy2 - T(3) * u2);
+  const T meq4 = rho * ux * (T(3) * uy2 - T(1));
+  const T meq6 = rho * uy * (T(3) * ux2 - T(1));
+  const T meq7 = rho * dxy, meq8 = rho * uxy;
+  const T Fu3 = T(3) * (Fx * ux + Fy * uy);
+  const T hF2 = T(9) * (Fx * ux * uy2 + Fy * uy * ux2) - Fu3;
+  const T hF4 = T(1.5) * (Fx * uy2 + T(2) * Fy * uxy) - T(0.5) * Fx;
+  const T hF6 = T(1.5) * (Fy * ux2 + T(2) * Fx * uxy) - T(0.5) * Fy;
+  const T hF7 = Fx * ux - Fy * uy;
+  const T hF8 = T(0.5) * (Fx * uy + Fy * ux);
+  const T d1 = m[1] - meq1 + Fu3, d2 = m[2] - meq2 + hF2, d4 = m[4] - meq4 + hF4;
+  const T d6 = m[6] - meq6 + hF6, d7 = m[7] - meq7 + hF7, d8 = m[8] - meq8 + hF8;
+  const T D1 = c.om_e * (d1 + c.k_seps_h * d2 + c.h_sq_h * (ux * d4 + uy * d6));
+  const T D7 = c.om_p * (d7 + c.b_sq * (ux * d4 - uy * d6));
+  const T D8 = c.om_p * (d8 + c.b_sq_h * (uy * d4 + ux * d6));
+  const T R11 = c.cR11 * u2, R17 = c.cR17 * dxy, R18 = c.cR18 * uxy;
+  const T t1x = ux * (c.cT1a * ux2 - c.cT1b * uy2), t1y = uy * (c.cT1a * uy2 - c.cT1b * ux2);
+  const T x1x = c.cX1 * uxy * uy, x1y = c.cX1 * uxy * ux;
+  const T R71 = c.cR71 * dxy, R77 = c.cR77 * u2;
+  const T t7x = c.cT7 * ux * (ux2 + c.two_b * uy2), t7y = -c.cT7 * uy * (uy2 + c.two_b * ux2);
+  const T x7x = c.cX7 * uxy * uy, x7y = -c.cX7 * uxy * ux;
+  const T R81 = c.cR81 * uxy, R88 = c.cR88 * u2;
+  const T v8x = uy * (uy2 + T(2) * ux2), v8y = ux * (ux2 + T(2) * uy2);
+  const T W8 = c.cT8 + dp * c.cX8, V8 = v8x * gx + v8y * gy;
+  const T gg = gx * gx + gy * gy;
+
+  // ---- lam of the post-collision moments: (M^-1)^T lam = D M lam ---------
+  T l[9];
+  forward_moments(lam, l);
+  l[0] *= T(1.0 / 9.0), l[1] *= T(1.0 / 36.0), l[2] *= T(1.0 / 36.0), l[3] *= T(1.0 / 6.0);
+  l[4] *= T(1.0 / 12.0), l[5] *= T(1.0 / 6.0), l[6] *= T(1.0 / 12.0), l[7] *= T(0.25), l[8] *= T(0.25);
+
+  T a_rho = l[0], a_ux = 0, a_uy = 0, a_Fx = l[3], a_Fy = l[5], a_dp = 0, a_eta = 0, a_g2 = 0;
+  T a_m[9] = {0, 0, 0, l[3], 0, l[5], 0, 0, 0};
+  a_gx = 0, a_gy = 0;
+  // post-collision rows (see collide_moments step (5)-(6))
+  T a_meq1 = l[1], a_hF1 = l[1], a_d1 = -l[1], a_D1 = T(2) * l[1], a_c1 = -l[1];
+  T a_gg = c.q1 * l[1] - c.s_eps * T(0.5) * c.g2 * l[2];
+  a_g2 += T(0.5) * (c.s_e - c.kq2) * gg * l[1] - c.s_eps * T(0.5) * gg * l[2];
+  T a_meq2 = l[2], a_hF2 = l[2], a_d2 = c.one_m_seps * l[2];
+  T a_meq4 = l[4], a_hF4 = l[4], a_d4 = c.one_m_sq * l[4];
+  T a_meq6 = l[6], a_hF6 = l[6], a_d6 = c.one_m_sq * l[6];
+  T a_meq7 = l[7], a_hF7 = l[7], a_d7 = -l[7], a_D7 = T(2) * l[7], a_c7 = -l[7];
+  a_gx += T(2) * c.q7 * gx * l[7], a_gy -= T(2) * c.q7 * gy * l[7];
+  a_g2 += c.s_p * T(1.0 / 12.0) * (gx * gx - gy * gy) * l[7];
+  T a_meq8 = l[8], a_hF8 = l[8], a_d8 = -l[8], a_D8 = T(2) * l[8], a_c8 = -l[8];
+  a_gx += c.q7 * gy * l[8], a_gy += c.q7 * gx * l[8];
+  a_g2 += c.s_p * T(1.0 / 12.0) * gx * gy * l[8];
+  a_gx += T(2) * gx * a_gg, a_gy += T(2) * gy * a_gg;
+
+  T a_u2 = 0, a_dxy = 0, a_uxy = 0, a_ux2 = 0, a_uy2 = 0;
+  // corr8 = R81 D1 + R88 D8 + W8 V8
+  {
+    a_uxy += c.cR81 * D1 * a_c8, a_D1 += R81 * a_c8;
+    a_u2 += c.cR88 * D8 * a_c8, a_D8 += R88 * a_c8;
+    a_dp += c.cX8 * V8 * a_c8;
+    const T a_V = W8 * a_c8;
+    const T a_v8x = gx * a_V, a_v8y = gy * a_V;
+    a_gx += v8x * a_V, a_gy += v8y * a_V;
+    a_ux += T(4) * uxy * a_v8x + (T(3) * ux2 + T(2) * uy2) * a_v8y;
+    a_uy += (T(3) * uy2 + T(2) * ux2) * a_v8x + T(4) * uxy * a_v8y;
+  }
+  // corr7 = R71 D1 + R77 D7 + (t7x + dp x7x) gx + (t7y + dp x7y) gy
+  {
+    a_dxy += c.cR71 * D1 * a_c7, a_D1 += R71 * a_c7;
+    a_u2 += c.cR77 * D7 * a_c7, a_D7 += R77 * a_c7;
+    a_dp += (x7x * gx + x7y * gy) * a_c7;
+    a_gx += (t7x + dp * x7x) * a_c7, a_gy += (t7y + dp * x7y) * a_c7;
+    const T a_t7x = gx * a_c7, a_t7y = gy * a_c7, a_x7x = dp * gx * a_c7, a_x7y = dp * gy * a_c7;
+    a_ux += c.cT7 * (T(3) * ux2 + c.two_b * uy2) * a_t7x - c.cT7 * T(2) * c.two_b * uxy * a_t7y;
+    a_uy += c.cT7 * T(2) * c.two_b * uxy * a_t7x - c.cT7 * (T(3) * uy2 + c.two_b * ux2) * a_t7y;
+    a_ux += c.cX7 * uy2 * a_x7x - T(2) * c.cX7 * uxy * a_x7y;
+    a_uy += T(2) * c.cX7 * uxy * a_x7x - c.cX7 * ux2 * a_x7y;
+  }
+  // corr1 = R11 D1 + R17 D7 + R18 D8 + (t1x + dp x1x) gx + (t1y + dp x1y) gy
+  {
+    a_u2 += c.cR11 * D1 * a_c1, a_D1 += R11 * a_c1;
+    a_dxy += c.cR17 * D7 * a_c1, a_D7 += R17 * a_c1;
+    a_uxy += c.cR18 * D8 * a_c1, a_D8 += R18 * a_c1;
+    a_dp += (x1x * gx + x1y * gy) * a_c1;
+    a_gx += (t1x + dp * x1x) * a_c1, a_gy += (t1y + dp * x1y) * a_c1;
+    const T a_t1x = gx * a_c1, a_t1y = gy * a_c1, a_x1x = dp * gx * a_c1, a_x1y = dp * gy * a_c1;
+    a_ux += (T(3) * c.cT1a * ux2 - c.cT1b * uy2) * a_t1x - T(2) * c.cT1b * uxy * a_t1y;
+    a_uy += -T(2) * c.cT1b * uxy * a_t1x + (T(3) * c.cT1a * uy2 - c.cT1b * ux2) * a_t1y;
+    a_ux += c.cX1 * uy2 * a_x1x + T(2) * c.cX1 * uxy * a_x1y;
+    a_uy += T(2) * c.cX1 * uxy * a_x1x + c.cX1 * ux2 * a_x1y;
+  }
+  // D8 = om_p (d8 + b_sq_h (uy d4 + ux d6))
+  {
+    a_d8 += c.om_p * a_D8;
+    const T t = c.om_p * c.b_sq_h * a_D8;
+    a_uy += d4 * t, a_d4 += uy * t, a_ux += d6 * t, a_d6 += ux * t;
+  }
+  // D7 = om_p (d7 + b_sq (ux d4 - uy d6))
+  {
+    a_d7 += c.om_p * a_D7;
+    const T t = c.om_p * c.b_sq * a_D7;
+    a_ux += d4 * t, a_d4 += ux * t, a_uy -= d6 * t, a_d6 -= uy * t;
+  }
+  // D1 = om_e (d1 + k_seps_h d2 + h_sq_h (ux d4 + uy d6))
+  {
+    a_d1 += c.om_e * a_D1;
+    a_d2 += c.om_e * c.k_seps_h * a_D1;
+    const T t = c.om_e * c.h_sq_h * a_D1;
+    a_ux += d4 * t, a_d4 += ux * t, a_uy += d6 * t, a_d6 += uy * t;
+  }
+  // d_k = m_k - meq_k + hF_k
+  a_m[1] += a_d1, a_meq1 -= a_d1, a_hF1 += a_d1;
+  a_m[2] += a_d2, a_meq2 -= a_d2, a_hF2 += a_d2;
+  a_m[4] += a_d4, a_meq4 -= a_d4, a_hF4 += a_d4;
+  a_m[6] += a_d6, a_meq6 -= a_d6, a_hF6 += a_d6;
+  a_m[7] += a_d7, a_meq7 -= a_d7, a_hF7 += a_d7;
+  a_m[8] += a_d8, a_meq8 -= a_d8, a_hF8 += a_d8;
+  // half force moments
+  a_Fx += T(0.5) * uy * a_hF8, a_uy += T(0.5) * Fx * a_hF8, a_Fy += T(0.5) * ux * a_hF8, a_ux += T(0.5) * Fy * a_hF8;
+  a_Fx += ux * a_hF7, a_ux += Fx * a_hF7, a_Fy -= uy * a_hF7, a_uy -= Fy * a_hF7;
+  a_Fy += (T(1.5) * ux2 - T(0.5)) * a_hF6, a_ux2 += T(1.5) * Fy * a_hF6, a_Fx += T(3) * uxy * a_hF6,
+      a_uxy += T(3) * Fx * a_hF6;
+  a_Fx += (T(1.5) * uy2 - T(0.5)) * a_hF4, a_uy2 += T(1.5) * Fx * a_hF4, a_Fy += T(3) * uxy * a_hF4,
+      a_uxy += T(3) * Fy * a_hF4;
+  T a_Fu3 = a_hF1 - a_hF2;
+  a_Fx += T(9) * ux * uy2 * a_hF2, a_ux += T(9) * Fx * uy2 * a_hF2, a_uy2 += T(9) * Fx * ux * a_hF2;
+  a_Fy += T(9) * uy * ux2 * a_hF2, a_uy += T(9) * Fy * ux2 * a_hF2, a_ux2 += T(9) * Fy * uy * a_hF2;
+  a_Fx += T(3) * ux * a_Fu3, a_ux += T(3) * Fx * a_Fu3, a_Fy += T(3) * uy * a_Fu3, a_uy += T(3) * Fy * a_Fu3;
+  // equilibrium moments
+  a_rho += uxy * a_meq8, a_uxy += rho * a_meq8;
+  a_rho += dxy * a_meq7, a_dxy += rho * a_meq7;
+  a_rho += uy * (T(3) * ux2 - T(1)) * a_meq6, a_uy += rho * (T(3) * ux2 - T(1)) * a_meq6,
+      a_ux2 += T(3) * rho * uy * a_meq6;
+  a_rho += ux * (T(3) * uy2 - T(1)) * a_meq4, a_ux += rho * (T(3) * uy2 - T(1)) * a_meq4,
+      a_uy2 += T(3) * rho * ux * a_meq4;
+  a_rho += (c.alpha2 + T(9) * ux2 * uy2 - T(3) * u2) * a_meq2, a_eta += c.beta2 * a_meq2;
+  a_ux2 += T(9) * rho * uy2 * a_meq2, a_uy2 += T(9) * rho * ux2 * a_meq2, a_u2 -= T(3) * rho * a_meq2;
+  a_eta += T(2) * a_meq1, a_rho += (T(3) * u2 - T(2)) * a_meq1, a_u2 += T(3) * rho * a_meq1;
+  // velocity products
+  a_ux2 += a_u2 + a_dxy, a_uy2 += a_u2 - a_dxy;
+  a_ux += uy * a_uxy + T(2) * ux * a_ux2;
+  a_uy += ux * a_uxy + T(2) * uy * a_uy2;
+  // ---- node state ----------------------------------------------------------
+  // eta = 3 p - rho;  dp = kprt dz + de_rho rho;  p = rho (kprt z + e_rho rho)
+  const T a_p = T(3) * a_eta;
+  a_rho -= a_eta;
+  const T a_dz = c.kprt * a_dp;
+  a_rho += c.de_rho * a_dp + (c.kprt * z + T(2) * c.e_rho * rho) * a_p;
+  const T a_z = rho * c.kprt * a_p;
+  const T a_kprt = dz * a_dp + rho * z * a_p;
+  const T a_erho = rho * rho * a_p, a_derho = rho * a_dp;
+  // z(rho) = Z(v) with d z / d rho = (dz - z)/rho (dz = d(rho Z)/d rho), and
+  // d dz / d rho = (b/4) (8 + 20 v - 4 v^2) / (1 - v)^5
+  a_rho += a_z * (dz - z) * inv + a_dz * c.b4 * (T(8) + v * (T(20) - T(4) * v)) * (iw3 * iw * iw);
+  // u = (j + F/2) / rho
+  a_m[3] += inv * a_ux, a_Fx += T(0.5) * inv * a_ux;
+  a_m[5] += inv * a_uy, a_Fy += T(0.5) * inv * a_uy;
+  a_rho -= (ux * a_ux + uy * a_uy) * inv;
+  // F = G'^2 rho g
+  a_rho += c.g2 * (gx * a_Fx + gy * a_Fy);
+  a_gx += c.g2 * rho * a_Fx, a_gy += c.g2 * rho * a_Fy;
+  a_g2 += rho * (gx * a_Fx + gy * a_Fy);
+  // parameters: kprt = K' RT, e_rho = G'^2/2 - K' a, de_rho = G'^2 - 2 K' a
+  a_th[0] += a_g2 + T(0.5) * a_erho + a_derho;
+  a_th[1] += c.rt * a_kprt - c.a * a_erho - T(2) * c.a * a_derho;
+  a_th[2] += c.kp * a_kprt;
+  // ---- populations: m = M f and rho = sum f ------------------------------
+  a_m[0] = a_rho;
+  transpose_moments(a_m, lam_f);
+}
+
+// Adjoint of the equilibrium initial state f^eq(rho0, u0, eta(rho0)) with
+// respect to rho0 (at fixed u0) and to (G'^2, K', R T), for lam = dL/d f^eq.
+template <typename T>
+__host__ __device__ __forceinline__ T equilibrium_vjp(T rho, T ux, T uy, const Coef<T>& c, const T* lam, T* a_th) {
+  // lam of the equilibrium moments: (M^-1)^T lam = D M lam
+  T l[9];
+  forward_moments(lam, l);
+  l[0] *= T(1.0 / 9.0), l[1] *= T(1.0 / 36.0), l[2] *= T(1.0 / 36.0), l[3] *= T(1.0 / 6.0);
+  l[4] *= T(1.0 / 12.0), l[5] *= T(1.0 / 6.0), l[6] *= T(1.0 / 12.0), l[7] *= T(0.25), l[8] *= T(0.25);
+  const T ux2 = ux * ux, uy2 = uy * uy, u2 = ux2 + uy2;
+  T p, dp;
+  eos(rho, c, p, dp);
+  const T v = c.b4 * rho;
+  const T iw = recip(T(1) - v);
+  const T z = (T(1) + v * (T(1) + v * (T(1) - v))) * (iw * iw * iw);
+  // d m^eq / d rho at fixed u and eta, and d m^eq / d eta
+  const T dm_rho = l[0] + (T(3) * u2 - T(2)) * l[1] + (c.alpha2 + T(9) * ux2 * uy2 - T(3) * u2) * l[2] +
+                   ux * l[3] + ux * (T(3) * uy2 - T(1)) * l[4] + uy * l[5] + uy * (T(3) * ux2 - T(1)) * l[6] +
+                   (ux2 - uy2) * l[7] + ux * uy * l[8];
+  const T a_eta = T(2) * l[1] + c.beta2 * l[2];
+  // eta = 3 p_LBE - rho:  d eta / d rho = 3 dp - 1;  p = K' rho (RT z - a rho) + G'^2 rho^2 / 2
+  a_th[0] += a_eta * T(1.5) * rho * rho;
+  a_th[1] += a_eta * T(3) * rho * (c.rt * z - c.a * rho);
+  a_th[2] += a_eta * T(3) * c.kp * rho * z;
+  return dm_rho + a_eta * (T(3) * dp - T(1));
+}
+
 }  // namespace lbm
