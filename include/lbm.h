@@ -14,18 +14,22 @@
  *    field sits at offset y*nx + x.  Distribution arrays are structure-of-
  *    arrays, population i (velocity order of supplement Eq. 3: rest, +x, +y,
  *    -x, -y, +x+y, -x+y, -x-y, +x-y) at offset i*nx*ny.
- *  - Pointers named f_*, rho*, u*, lam*, drho* are DEVICE pointers owned by
- *    the caller (any allocator; the library never frees them).  Pointers
- *    named *_out, totals, dtheta, out are HOST pointers.
+ *  - Field and buffer pointers (f, f_*, rho*, u*, lam, adj*, drho0, src,
+ *    dst) are DEVICE pointers owned by the caller (any allocator; the
+ *    library never frees them).  The result pointers out, sigma_out,
+ *    totals, dtheta and jac are HOST pointers.
  *  - Every call is asynchronous on the stream given to lbm_create (or
- *    lbm_set_stream), except where stated: lbm_init and lbm_moments
- *    synchronise that stream to return host results.
+ *    lbm_set_stream), except where stated: lbm_init, lbm_moments (with
+ *    totals) and lbm_adjoint_theta (with dtheta) synchronise that stream to
+ *    return host results.
  *  - Every int-returning call returns LBM_OK (0) or a negative status;
  *    lbm_last_error() then returns a message for the calling thread.  A
  *    failed call launches nothing and leaves the state unchanged, except
  *    LBM_EHIP (a HIP runtime error), after which the state is undefined.
  *  - The library allocates only small device scratch inside the context
- *    (reduction partials and a status word); lbm_destroy frees it.
+ *    (reduction partials, the parameter-gradient accumulator and a status
+ *    word), cleared on the stream at lbm_create; lbm_destroy frees it.
+ *    Every state, checkpoint and adjoint buffer belongs to the caller.
  */
 #ifndef LBM_H
 #define LBM_H
@@ -121,8 +125,9 @@ size_t lbm_ref_bytes(const lbm_params* p);
 /* Create a context over caller-owned device buffers f_a, f_b (each
  * lbm_state_bytes) and rho_ref (lbm_ref_bytes; may be NULL for LBM_FP32),
  * on HIP stream `stream` (a hipStream_t; NULL = default stream), on the
- * current HIP device.  Derives the coefficients; launches nothing.  The
- * state is uninitialised until lbm_init or lbm_set_state. */
+ * current HIP device.  Derives the coefficients and clears the context's
+ * scratch on the stream.  The state is uninitialised until lbm_init,
+ * lbm_set_state or lbm_load_state. */
 int lbm_create(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b,
                void* rho_ref, void* stream);
 
@@ -153,6 +158,80 @@ int lbm_step(lbm_ctx* ctx, int32_t n);
  * deterministically on the device (synchronises the stream).  Returns
  * LBM_ENONFINITE if a total is not finite. */
 int lbm_moments(lbm_ctx* ctx, float* rho, float* ux, float* uy, double totals[3]);
+
+/* ---- Checkpoints --------------------------------------------------------
+ * A checkpoint is the library's own copy of the current state: the pull
+ * buffer (lbm_state_bytes) followed, for the 2-byte storages, by the
+ * reference-density plane (2*nx*ny bytes).  Its layout is internal. */
+
+/* Bytes of one checkpoint buffer; 0 on error. */
+size_t lbm_checkpoint_bytes(const lbm_params* p);
+
+/* Copy the current state into the device buffer dst (lbm_checkpoint_bytes). */
+int lbm_save_state(lbm_ctx* ctx, void* dst);
+
+/* Make a checkpoint the current state and set the step counter to t >= 0.
+ * Stepping from it repeats the run it was saved from bit for bit. */
+int lbm_load_state(lbm_ctx* ctx, const void* src, int64_t t);
+
+/* One step from the checkpoint src into the checkpoint dst (distinct device
+ * buffers) with the kernel of lbm_step, so dst is bitwise what lbm_step
+ * would leave; the context's own state is not touched.  This is the
+ * recomputation of a checkpoint segment for the adjoint.  LBM_FP32 only. */
+int lbm_step_saved(lbm_ctx* ctx, const void* src, void* dst);
+
+/* ---- Adjoint (reverse mode) of a rollout; LBM_FP32 storage only ---------
+ * For a scalar loss L of the state, the adjoint of time t is
+ * Lambda_i(x, t) = dL/d f_i(x, t) of the post-streaming populations.  One
+ * adjoint step maps Lambda(t+1) to Lambda(t) = (d step / d f(t))^T Lambda(t+1)
+ * (the transposed Jacobian of the step of main Eq. 13 with the force of main
+ * Eq. 12 and streaming, supplement Eq. 2) and adds Lambda(t+1) .
+ * d step / d theta to the context's FP64 accumulator of dL/d theta,
+ * theta = (G'^2, K', R T).
+ *
+ * Adjoint states live in caller-owned device buffers of lbm_adjoint_bytes
+ * (eleven FP32 planes of nx*ny in an internal layout: Lambda is held as nine
+ * planes plus the two-component adjoint of the force-stencil gradient, which
+ * the next step scatters to the neighbour densities).  lbm_adjoint_seed and
+ * lbm_adjoint_get convert from and to plain Lambda arrays in the SoA layout
+ * of the populations.  The accumulator starts at zero when the context is
+ * created and is summed and cleared by lbm_adjoint_theta.  Accumulation and
+ * its sum run in a fixed order: repeated runs give identical bits. */
+
+/* Bytes of one adjoint state buffer (11*nx*ny*4); 0 for the 2-byte
+ * storages or on error. */
+size_t lbm_adjoint_bytes(const lbm_params* p);
+
+/* adj := the adjoint state of Lambda = lam (device float, 9*nx*ny). */
+int lbm_adjoint_seed(lbm_ctx* ctx, const float* lam, void* adj);
+
+/* One adjoint step: f_t is the checkpoint of the forward state at time t
+ * (lbm_save_state or lbm_step_saved), adj_next the adjoint state of time
+ * t+1, adj_out (a different buffer) receives that of time t.  Adds the
+ * theta terms of this step to the accumulator. */
+int lbm_adjoint_step(lbm_ctx* ctx, const void* f_t, const void* adj_next, void* adj_out);
+
+/* lam := Lambda of the adjoint state adj (device float, 9*nx*ny). */
+int lbm_adjoint_get(lbm_ctx* ctx, const void* adj, float* lam);
+
+/* Adjoint of the initial state f_i(x, 0) = f_i^eq(rho0(x), u0(x), eta(rho0))
+ * of lbm_init: drho0(x) = sum_i Lambda_i(x, 0) d f_i^eq / d rho0 (u0 held
+ * fixed; ux0 / uy0 NULL means zero) from the adjoint state adj0 of time 0;
+ * adds the theta terms of eta(rho0; theta) to the accumulator.  rho0, ux0,
+ * uy0 and drho0 are device float fields of nx*ny. */
+int lbm_adjoint_init(lbm_ctx* ctx, const float* rho0, const float* ux0, const float* uy0, const void* adj0,
+                     float* drho0);
+
+/* If dtheta is not NULL, write the accumulated dL/d(G'^2, K', R T) there
+ * (synchronises the stream); then clear the accumulator if reset != 0.
+ * LBM_ENONFINITE if a component is not finite. */
+int lbm_adjoint_theta(lbm_ctx* ctx, double dtheta[3], int32_t reset);
+
+/* Host-only: jac[3*k + j] = d theta_k / d (sigma, W, T_r)_j at the point of
+ * *p (main Eqs. 20, 21, 23), with sigma the value lbm_derive reports, held
+ * independent of W and T_r.  The T_r column differentiates the flat-
+ * interface constants numerically (fourth-order central difference). */
+int lbm_param_jacobian(const lbm_params* p, double jac[9]);
 
 /* Number of steps taken since lbm_init / lbm_set_state. */
 int64_t lbm_time(const lbm_ctx* ctx);

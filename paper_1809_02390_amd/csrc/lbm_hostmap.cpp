@@ -255,4 +255,36 @@ int derive(const lbm_params* p, lbm_derived* o, char* msg, size_t len) {
   return LBM_OK;
 }
 
+// d(G'^2, K', R T) / d(sigma, W, T_r), row-major 3 x 3.  With
+// K_INT = W / C_W and K_EOS = sigma / (C_sigma K_INT) (main Eqs. 21, 23):
+//   G'^2 = 2 a sigma W / (C_sigma C_W),  K' = sigma C_W / (C_sigma W),  R T = R T_r T_c,
+// so only d C_sigma / d T_r and d C_W / d T_r are not closed forms; they are
+// taken by the fourth-order central difference of interface_constants (a
+// smooth function: fixed Gauss-Legendre panels and roots to the last bit).
+// sigma is the value the context uses (prescribed or the default rule) and
+// is held independent of W and T_r.
+int param_jacobian(const lbm_params* p, double* jac, char* msg, size_t len) {
+  lbm_derived d;
+  int st = derive(p, &d, msg, len);
+  if (st) return st;
+  const double tr = p->tr, h = 1e-3 * std::fmin(tr, 1.0 - tr);
+  double cs[4], cw[4];
+  const double off[4] = {-2.0, -1.0, 1.0, 2.0};
+  for (int k = 0; k < 4; ++k) {
+    st = interface_constants(tr + off[k] * h, p->a, p->b, p->r_gas, &cs[k], &cw[k]);
+    if (st) {
+      std::snprintf(msg, len, "no two-phase coexistence near tr = %g", tr);
+      return st;
+    }
+  }
+  const double dcs = (cs[0] - 8.0 * cs[1] + 8.0 * cs[2] - cs[3]) / (12.0 * h);
+  const double dcw = (cw[0] - 8.0 * cw[1] + 8.0 * cw[2] - cw[3]) / (12.0 * h);
+  const double ls = dcs / d.c_sigma, lw = dcw / d.c_w;
+  const double J[9] = {d.g2 / d.sigma, d.g2 / d.width, -d.g2 * (ls + lw),
+                       d.kp / d.sigma, -d.kp / d.width, d.kp * (lw - ls),
+                       0.0,            0.0,             p->r_gas * d.tc};
+  for (int k = 0; k < 9; ++k) jac[k] = J[k];
+  return LBM_OK;
+}
+
 }  // namespace lbm

@@ -13,5 +13,6 @@ int interface_constants(double tr, double a, double b, double r_gas, double* c_s
 int sigma_paper(double width, double tr, double a, double b, double r_gas, double* sigma);
 int validate(const lbm_params* p, char* msg, size_t len);
 int derive(const lbm_params* p, lbm_derived* out, char* msg, size_t len);
+int param_jacobian(const lbm_params* p, double* jac, char* msg, size_t len);
 
 }  // namespace lbm

@@ -510,6 +510,185 @@ __global__ __launch_bounds__(BLK) void get_state_kernel(const void* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint (reverse mode) of the FP32 step
+//
+// The adjoint of time t is Lambda_i(x) = dL/d f_i(x, t) for the post-
+// streaming populations.  It is kept as eleven planes {L_0..L_8, A_x, A_y}:
+//   Lambda_i(x) = L_i(x) + nu(x),   nu(z) = sum_j w_j e_j . A(z - e_j),
+// where A(y) = dL/d g(y) for the stencil gradient g of main Eq. 12 at y and
+// nu(z) is dL/d rho(z) through the eight stencils that read rho(z).  Keeping
+// A instead of adding nu to all nine planes saves a second sweep: the next
+// adjoint step forms nu on its tile from a two-node halo of A.
+//
+// One adjoint step, for every node y (forward state of time t, adjoint of
+// time t+1):
+//   lam-bar_i(y) = Lambda_i(y + e_i, t+1)   (streaming moved f-bar_i(y) to y + e_i)
+//   (L_i(y), A(y), dtheta) = transposed Jacobian of the collision at y
+//                            (rho and g recomputed as the forward step has them)
+// ---------------------------------------------------------------------------
+using AdjTile = TileShape<128, 8, 4>;
+
+template <class S>
+struct AdjLds {
+  static constexpr int AW = S::TX + 4, AH = S::TY + 4, NA = AW * AH;
+  static constexpr int NRED = 3 * S::NTHREADS;  // doubles of the block reduction
+  static_assert(NRED * 2 <= 2 * NA, "reduction reuses the A halo");
+};
+
+// A on the tile plus a two-node ring into sa[2][AH][AW], then nu on the tile
+// plus a one-node ring into snu[(TY+2)][LW].  Ends with a barrier.
+template <class S>
+__device__ __forceinline__ void stage_nu(const float* __restrict__ ax, const float* __restrict__ ay, int nx, int ny,
+                                         int x0, int y0, float* sa, float* snu) {
+  using L = AdjLds<S>;
+  const int tid = threadIdx.y * S::TX + threadIdx.x;
+  for (int p = tid; p < L::NA; p += S::NTHREADS) {
+    const int hx = p % L::AW, hy = p / L::AW;
+    const size_t o = (size_t)wrap(y0 + hy - 2, ny) * nx + wrap(x0 + hx - 2, nx);
+    sa[p] = ax[o];
+    sa[L::NA + p] = ay[o];
+  }
+  __syncthreads();
+  const float third = 1.0f / 3.0f, twelfth = 1.0f / 12.0f;
+  const float* sx = sa;
+  const float* sy = sa + L::NA;
+  for (int p = tid; p < S::LDS; p += S::NTHREADS) {
+    const int hx = p % S::LW, hy = p / S::LW;
+    const int c = (hy + 1) * L::AW + hx + 1;  // the same node in the A halo
+    // axis neighbours z - e_j: E -> c-1, W -> c+1, N -> c-AW, S -> c+AW
+    const float axis = (sx[c - 1] - sx[c + 1]) + (sy[c - L::AW] - sy[c + L::AW]);
+    // diagonals: NE -> c-AW-1 (Ax+Ay), NW -> c-AW+1 (Ay-Ax), SW -> c+AW+1 -(Ax+Ay), SE -> c+AW-1 (Ax-Ay)
+    const float diag = (sx[c - L::AW - 1] + sy[c - L::AW - 1]) + (sy[c - L::AW + 1] - sx[c - L::AW + 1]) -
+                       (sx[c + L::AW + 1] + sy[c + L::AW + 1]) + (sx[c + L::AW - 1] - sy[c + L::AW - 1]);
+    snu[p] = third * axis + twelfth * diag;
+  }
+  __syncthreads();
+}
+
+// Deterministic FP64 block sum of three per-thread values, added to this
+// block's slot of partials (a block always owns the same slot, so sums over
+// many launches are reproducible bit for bit).
+template <class S>
+__device__ __forceinline__ void block_accumulate(const float* th, double* red, double* __restrict__ partials) {
+  const int tid = threadIdx.y * S::TX + threadIdx.x;
+  __syncthreads();  // red aliases LDS read above
+#pragma unroll
+  for (int k = 0; k < 3; ++k) red[k * S::NTHREADS + tid] = (double)th[k];
+  __syncthreads();
+  for (int w = S::NTHREADS / 2; w > 0; w >>= 1) {
+    if (tid < w)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) red[k * S::NTHREADS + tid] += red[k * S::NTHREADS + tid + w];
+    __syncthreads();
+  }
+  if (tid < 3) partials[(size_t)blockIdx.x * 3 + tid] += red[tid * S::NTHREADS];
+}
+
+template <class S>
+__global__ __launch_bounds__(S::NTHREADS) void adjoint_step_kernel(const float* __restrict__ fsrc,
+                                                                   const float* __restrict__ adj_in,
+                                                                   float* __restrict__ adj_out,
+                                                                   double* __restrict__ partials, int nx, int ny,
+                                                                   int ntx, int ntiles, Coef<float> c) {
+  using L = AdjLds<S>;
+  __shared__ float srho[S::LDS];
+  __shared__ float snu[S::LDS];
+  __shared__ __align__(8) float sa[2 * L::NA];
+  const size_t N = (size_t)nx * ny;
+  const int tile = xcd_tile(blockIdx.x, ntiles);
+  const int x0 = (tile % ntx) * S::TX, y0 = (tile / ntx) * S::TY;
+  float f[S::NPT][9];
+  double mass[S::NPT];
+  {
+    TileRegs<S, StoreF32> R;
+    issue_tile<S, StoreF32>(planes<float>(fsrc, N), nullptr, nx, ny, x0, y0, R);
+    stage_tile<S, StoreF32>(R, RefPoly<float>{}, f, mass, srho, nullptr);
+  }
+  stage_nu<S>(adj_in + 9 * N, adj_in + 10 * N, nx, ny, x0, y0, sa, snu);  // barrier covers srho too
+  const Planes<float> P = planes<float>(adj_in, N);
+  float th[3] = {0.0f, 0.0f, 0.0f};
+  const int x = x0 + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < S::NPT; ++k) {
+    const int ly = threadIdx.y + k * S::WY, y = y0 + ly;
+    if (x >= nx || y >= ny) break;
+    const int hx = threadIdx.x + 1, hy = ly + 1, pos = hy * S::LW + hx;
+    float nb[9];
+    neighbours<S>(srho, hx, hy, nb);
+    float gx, gy;
+    stencil(nb[1], nb[2], nb[3], nb[4], nb[5], nb[6], nb[7], nb[8], gx, gy);
+    // lam-bar_i(y) = L_i(y + e_i) + nu(y + e_i)
+    const NodeAddr<4> a = node_addr<4>(x, y, nx, ny);
+    float lb[9];
+    lb[0] = ldb<float>(P.p[0], a.r0 + a.c0);
+    lb[1] = ldb<float>(P.p[1], a.r0 + a.cp);
+    lb[2] = ldb<float>(P.p[2], a.rp + a.c0);
+    lb[3] = ldb<float>(P.p[3], a.r0 + a.cm);
+    lb[4] = ldb<float>(P.p[4], a.rm + a.c0);
+    lb[5] = ldb<float>(P.p[5], a.rp + a.cp);
+    lb[6] = ldb<float>(P.p[6], a.rp + a.cm);
+    lb[7] = ldb<float>(P.p[7], a.rm + a.cm);
+    lb[8] = ldb<float>(P.p[8], a.rm + a.cp);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) lb[i] += snu[pos + kCy[i] * S::LW + kCx[i]];
+    float lf[9], agx = 0.0f, agy = 0.0f;
+    collide_node_vjp<float>(f[k], gx, gy, c, lb, lf, agx, agy, th);
+    const size_t o = (size_t)y * nx + x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(lf[i], adj_out + (size_t)i * N + o);
+    __builtin_nontemporal_store(agx, adj_out + 9 * N + o);
+    __builtin_nontemporal_store(agy, adj_out + 10 * N + o);
+  }
+  block_accumulate<S>(th, reinterpret_cast<double*>(sa), partials);
+}
+
+// Lambda = L + nu on the tile, then either exported (kInit false) or taken
+// through the adjoint of the initial equilibrium (kInit true): dL/d rho0 and
+// the parameter terms that enter through eta(rho0).
+template <class S, bool kInit>
+__global__ __launch_bounds__(S::NTHREADS) void adjoint_finish_kernel(
+    const float* __restrict__ adj, float* __restrict__ out, const float* __restrict__ rho0,
+    const float* __restrict__ ux0, const float* __restrict__ uy0, double* __restrict__ partials, int nx, int ny,
+    int ntx, Coef<float> c) {
+  using L = AdjLds<S>;
+  __shared__ float snu[S::LDS];
+  __shared__ __align__(8) float sa[2 * L::NA];
+  const size_t N = (size_t)nx * ny;
+  const int x0 = (blockIdx.x % ntx) * S::TX, y0 = (blockIdx.x / ntx) * S::TY;
+  stage_nu<S>(adj + 9 * N, adj + 10 * N, nx, ny, x0, y0, sa, snu);
+  float th[3] = {0.0f, 0.0f, 0.0f};
+  const int x = x0 + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < S::NPT; ++k) {
+    const int ly = threadIdx.y + k * S::WY, y = y0 + ly;
+    if (x >= nx || y >= ny) break;
+    const float nu = snu[(ly + 1) * S::LW + threadIdx.x + 1];
+    const size_t o = (size_t)y * nx + x;
+    float lam[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) lam[i] = adj[(size_t)i * N + o] + nu;
+    if constexpr (kInit) {
+      out[o] = equilibrium_vjp<float>(rho0[o], ux0 ? ux0[o] : 0.0f, uy0 ? uy0[o] : 0.0f, c, lam, th);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) out[(size_t)i * N + o] = lam[i];
+    }
+  }
+  if constexpr (kInit) block_accumulate<S>(th, reinterpret_cast<double*>(sa), partials);
+}
+
+// Adjoint state from a plain Lambda: L = lam, A = 0.
+__global__ __launch_bounds__(BLK) void adjoint_seed_kernel(const float* __restrict__ lam, float* __restrict__ adj,
+                                                          size_t N) {
+  const size_t o = (size_t)blockIdx.x * BLK + threadIdx.x;
+  if (o >= N) return;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) adj[(size_t)i * N + o] = lam[(size_t)i * N + o];
+  adj[9 * N + o] = 0.0f;
+  adj[10 * N + o] = 0.0f;
+}
+
+// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 Coef<float> make_coef(const lbm_derived& d, double varpi, double a, double b) {
@@ -643,6 +822,8 @@ struct lbm_ctx {
   int nblocks;       // workgroups of the moments tile grid
   double* scratch;   // nblocks*3 partials, then 3 totals
   int* flag;
+  int adj_blocks;    // workgroups of the adjoint tile grid
+  double* theta;     // adj_blocks*3 accumulated partials of dL/dtheta, then 3 totals
 };
 
 namespace {
@@ -733,13 +914,19 @@ int lbm_create(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, void* r
   c->t = 0;
   c->stream = (hipStream_t)stream;
   c->nblocks = tiles_total<MomTile>(p->nx, p->ny);
+  c->adj_blocks = p->storage == LBM_FP32 ? tiles_total<AdjTile>(p->nx, p->ny) : 0;
+  const size_t mom_doubles = 3 * (size_t)c->nblocks + 3 + 8;  // + the status word
+  const size_t th_doubles = 3 * (size_t)c->adj_blocks + 3;
   hipError_t e = hipGetDevice(&c->device);
-  if (e == hipSuccess) e = hipMalloc(&c->scratch, sizeof(double) * (3 * (size_t)c->nblocks + 3) + 64);
+  if (e == hipSuccess) e = hipMalloc(&c->scratch, sizeof(double) * (mom_doubles + th_doubles));
+  if (e == hipSuccess) e = hipMemsetAsync(c->scratch, 0, sizeof(double) * (mom_doubles + th_doubles), c->stream);
   if (e != hipSuccess) {
+    if (c->scratch) (void)hipFree(c->scratch);
     delete c;
     return fail(LBM_EHIP, "lbm_create: %s", hipGetErrorString(e));
   }
   c->flag = reinterpret_cast<int*>(c->scratch + 3 * (size_t)c->nblocks + 3);
+  c->theta = c->scratch + mom_doubles;
   *out = c;
   return LBM_OK;
 }
@@ -856,6 +1043,142 @@ int lbm_moments(lbm_ctx* ctx, float* rho, float* ux, float* uy, double totals[3]
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(totals[k])) return fail(LBM_ENONFINITE, "non-finite total (%d): the state has diverged", k);
   return LBM_OK;
+}
+
+size_t lbm_checkpoint_bytes(const lbm_params* p) {
+  const size_t s = lbm_state_bytes(p);
+  return s == 0 || p->storage == LBM_FP32 ? s : s + (size_t)2 * p->nx * p->ny;
+}
+
+int lbm_save_state(lbm_ctx* ctx, void* dst) {
+  if (int st = check_ctx(ctx, true)) return st;
+  if (!dst) return fail(LBM_EINVAL, "dst is NULL");
+  if (int st = set_device(ctx)) return st;
+  const size_t sb = lbm_state_bytes(&ctx->p);
+  HIP_OK(hipMemcpyAsync(dst, ctx->buf[ctx->cur], sb, hipMemcpyDeviceToDevice, ctx->stream));
+  if (ctx->p.storage != LBM_FP32)
+    HIP_OK(hipMemcpyAsync(static_cast<char*>(dst) + sb, ctx->ref[ctx->cur], (size_t)2 * ctx->p.nx * ctx->p.ny,
+                          hipMemcpyDeviceToDevice, ctx->stream));
+  return LBM_OK;
+}
+
+int lbm_load_state(lbm_ctx* ctx, const void* src, int64_t t) {
+  if (int st = check_ctx(ctx, false)) return st;
+  if (!src) return fail(LBM_EINVAL, "src is NULL");
+  if (t < 0) return fail(LBM_EINVAL, "t must be >= 0");
+  if (int st = set_device(ctx)) return st;
+  const size_t sb = lbm_state_bytes(&ctx->p);
+  HIP_OK(hipMemcpyAsync(ctx->buf[0], src, sb, hipMemcpyDeviceToDevice, ctx->stream));
+  if (ctx->p.storage != LBM_FP32)
+    HIP_OK(hipMemcpyAsync(ctx->ref[0], static_cast<const char*>(src) + sb, (size_t)2 * ctx->p.nx * ctx->p.ny,
+                          hipMemcpyDeviceToDevice, ctx->stream));
+  ctx->cur = 0;
+  ctx->t = t;
+  ctx->ready = true;
+  return LBM_OK;
+}
+
+namespace {
+int need_fp32(const lbm_ctx* ctx, const char* what) {
+  if (ctx->p.storage != LBM_FP32) return fail(LBM_EINVAL, "%s is available for LBM_FP32 storage only", what);
+  return LBM_OK;
+}
+}  // namespace
+
+int lbm_step_saved(lbm_ctx* ctx, const void* src, void* dst) {
+  if (int st = check_ctx(ctx, false)) return st;
+  if (int st = need_fp32(ctx, "lbm_step_saved")) return st;
+  if (!src || !dst || src == dst) return fail(LBM_EINVAL, "src and dst must be two distinct device buffers");
+  if (int st = set_device(ctx)) return st;
+  using S = StepTile;
+  step_kernel<S, StoreF32><<<tiles_total<S>(ctx->p.nx, ctx->p.ny), dim3(S::TX, S::WY), 0, ctx->stream>>>(
+      src, dst, nullptr, nullptr, ctx->p.nx, ctx->p.ny, tiles_x<S>(ctx->p.nx), tiles_total<S>(ctx->p.nx, ctx->p.ny),
+      ctx->c, ctx->q);
+  HIP_OK(hipGetLastError());
+  return LBM_OK;
+}
+
+size_t lbm_adjoint_bytes(const lbm_params* p) {
+  char msg[256];
+  if (lbm::validate(p, msg, sizeof msg) || p->storage != LBM_FP32) return 0;
+  return (size_t)11 * p->nx * p->ny * sizeof(float);
+}
+
+int lbm_adjoint_seed(lbm_ctx* ctx, const float* lam, void* adj) {
+  if (int st = check_ctx(ctx, false)) return st;
+  if (int st = need_fp32(ctx, "the adjoint")) return st;
+  if (!lam || !adj) return fail(LBM_EINVAL, "lam and adj must be device buffers");
+  if (int st = set_device(ctx)) return st;
+  const size_t N = (size_t)ctx->p.nx * ctx->p.ny;
+  adjoint_seed_kernel<<<grid1(N), BLK, 0, ctx->stream>>>(lam, static_cast<float*>(adj), N);
+  HIP_OK(hipGetLastError());
+  return LBM_OK;
+}
+
+int lbm_adjoint_step(lbm_ctx* ctx, const void* f_t, const void* adj_next, void* adj_out) {
+  if (int st = check_ctx(ctx, false)) return st;
+  if (int st = need_fp32(ctx, "the adjoint")) return st;
+  if (!f_t || !adj_next || !adj_out || adj_next == adj_out)
+    return fail(LBM_EINVAL, "f_t, adj_next and adj_out must be device buffers, adj_next != adj_out");
+  if (int st = set_device(ctx)) return st;
+  using S = AdjTile;
+  const int ntx = tiles_x<S>(ctx->p.nx), ntiles = ctx->adj_blocks;
+  adjoint_step_kernel<S><<<ntiles, dim3(S::TX, S::WY), 0, ctx->stream>>>(
+      static_cast<const float*>(f_t), static_cast<const float*>(adj_next), static_cast<float*>(adj_out),
+      ctx->theta, ctx->p.nx, ctx->p.ny, ntx, ntiles, ctx->c);
+  HIP_OK(hipGetLastError());
+  return LBM_OK;
+}
+
+int lbm_adjoint_get(lbm_ctx* ctx, const void* adj, float* lam) {
+  if (int st = check_ctx(ctx, false)) return st;
+  if (int st = need_fp32(ctx, "the adjoint")) return st;
+  if (!adj || !lam) return fail(LBM_EINVAL, "adj and lam must be device buffers");
+  if (int st = set_device(ctx)) return st;
+  using S = AdjTile;
+  adjoint_finish_kernel<S, false><<<ctx->adj_blocks, dim3(S::TX, S::WY), 0, ctx->stream>>>(
+      static_cast<const float*>(adj), lam, nullptr, nullptr, nullptr, nullptr, ctx->p.nx, ctx->p.ny,
+      tiles_x<S>(ctx->p.nx), ctx->c);
+  HIP_OK(hipGetLastError());
+  return LBM_OK;
+}
+
+int lbm_adjoint_init(lbm_ctx* ctx, const float* rho0, const float* ux0, const float* uy0, const void* adj0,
+                     float* drho0) {
+  if (int st = check_ctx(ctx, false)) return st;
+  if (int st = need_fp32(ctx, "the adjoint")) return st;
+  if (!rho0 || !adj0 || !drho0) return fail(LBM_EINVAL, "rho0, adj0 and drho0 must be device buffers");
+  if (int st = set_device(ctx)) return st;
+  using S = AdjTile;
+  adjoint_finish_kernel<S, true><<<ctx->adj_blocks, dim3(S::TX, S::WY), 0, ctx->stream>>>(
+      static_cast<const float*>(adj0), drho0, rho0, ux0, uy0, ctx->theta, ctx->p.nx, ctx->p.ny,
+      tiles_x<S>(ctx->p.nx), ctx->c);
+  HIP_OK(hipGetLastError());
+  return LBM_OK;
+}
+
+int lbm_adjoint_theta(lbm_ctx* ctx, double dtheta[3], int32_t reset) {
+  if (int st = check_ctx(ctx, false)) return st;
+  if (int st = need_fp32(ctx, "the adjoint")) return st;
+  if (int st = set_device(ctx)) return st;
+  double* tot = ctx->theta + 3 * (size_t)ctx->adj_blocks;
+  if (dtheta) {
+    finish_sums<<<1, RED, 0, ctx->stream>>>(ctx->theta, ctx->adj_blocks, tot);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(dtheta, tot, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  }
+  if (reset) HIP_OK(hipMemsetAsync(ctx->theta, 0, 3 * sizeof(double) * (size_t)ctx->adj_blocks, ctx->stream));
+  if (dtheta) {
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(dtheta[k])) return fail(LBM_ENONFINITE, "non-finite parameter gradient (%d)", k);
+  }
+  return LBM_OK;
+}
+
+int lbm_param_jacobian(const lbm_params* p, double jac[9]) {
+  if (!jac) return fail(LBM_EINVAL, "jac is NULL");
+  return lbm::param_jacobian(p, jac, g_err, sizeof g_err);
 }
 
 int64_t lbm_time(const lbm_ctx* ctx) { return ctx ? ctx->t : -1; }

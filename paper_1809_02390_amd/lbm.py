@@ -62,6 +62,17 @@ def _load():
         "lbm_get_state": (I, [V, V]),
         "lbm_step": (I, [V, ctypes.c_int32]),
         "lbm_moments": (I, [V, V, V, V, P(D)]),
+        "lbm_checkpoint_bytes": (ctypes.c_size_t, [P(lbm_params)]),
+        "lbm_save_state": (I, [V, V]),
+        "lbm_load_state": (I, [V, V, ctypes.c_int64]),
+        "lbm_step_saved": (I, [V, V, V]),
+        "lbm_adjoint_bytes": (ctypes.c_size_t, [P(lbm_params)]),
+        "lbm_adjoint_seed": (I, [V, V, V]),
+        "lbm_adjoint_step": (I, [V, V, V, V]),
+        "lbm_adjoint_get": (I, [V, V, V]),
+        "lbm_adjoint_init": (I, [V, V, V, V, V, V]),
+        "lbm_adjoint_theta": (I, [V, P(D), ctypes.c_int32]),
+        "lbm_param_jacobian": (I, [P(lbm_params), P(D)]),
         "lbm_time": (ctypes.c_int64, [V]),
         "lbm_get_derived": (I, [V, P(lbm_derived)]),
         "lbm_destroy": (None, [V]),
@@ -76,7 +87,9 @@ def _load():
 _lib = _load()
 EXPORTED = ("lbm_last_error", "lbm_derive", "lbm_sigma_paper", "lbm_state_bytes", "lbm_ref_bytes",
             "lbm_create", "lbm_set_stream", "lbm_init", "lbm_set_state", "lbm_get_state", "lbm_step",
-            "lbm_moments", "lbm_time", "lbm_get_derived", "lbm_destroy")
+            "lbm_moments", "lbm_checkpoint_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_saved",
+            "lbm_adjoint_bytes", "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_get", "lbm_adjoint_init",
+            "lbm_adjoint_theta", "lbm_param_jacobian", "lbm_time", "lbm_get_derived", "lbm_destroy")
 
 
 def _check(status: int):
@@ -179,6 +192,65 @@ def lbm_moments(ctx, rho=None, ux=None, uy=None, totals=True, n=None):
     return tuple(tot) if totals else None
 
 
+def lbm_checkpoint_bytes(params: lbm_params) -> int:
+    return _lib.lbm_checkpoint_bytes(ctypes.byref(params))
+
+
+def _bytes_ptr(t, nbytes, name):
+    p = _ptr(t, name=name)
+    if t.numel() * t.element_size() < nbytes:
+        raise ValueError(f"{name} must hold at least {nbytes} bytes")
+    return p
+
+
+def lbm_save_state(ctx, dst, nbytes):
+    _check(_lib.lbm_save_state(ctx, _bytes_ptr(dst, nbytes, "dst")))
+
+
+def lbm_load_state(ctx, src, t, nbytes):
+    _check(_lib.lbm_load_state(ctx, _bytes_ptr(src, nbytes, "src"), int(t)))
+
+
+def lbm_step_saved(ctx, src, dst, nbytes):
+    _check(_lib.lbm_step_saved(ctx, _bytes_ptr(src, nbytes, "src"), _bytes_ptr(dst, nbytes, "dst")))
+
+
+def lbm_adjoint_bytes(params: lbm_params) -> int:
+    return _lib.lbm_adjoint_bytes(ctypes.byref(params))
+
+
+def lbm_adjoint_seed(ctx, lam, adj, n):
+    _check(_lib.lbm_adjoint_seed(ctx, _ptr(lam, torch.float32, 9 * n, "lam"), _bytes_ptr(adj, 44 * n, "adj")))
+
+
+def lbm_adjoint_step(ctx, f_t, adj_next, adj_out, n, state_bytes):
+    _check(_lib.lbm_adjoint_step(ctx, _bytes_ptr(f_t, state_bytes, "f_t"), _bytes_ptr(adj_next, 44 * n, "adj_next"),
+                                 _bytes_ptr(adj_out, 44 * n, "adj_out")))
+
+
+def lbm_adjoint_get(ctx, adj, lam, n):
+    _check(_lib.lbm_adjoint_get(ctx, _bytes_ptr(adj, 44 * n, "adj"), _ptr(lam, torch.float32, 9 * n, "lam")))
+
+
+def lbm_adjoint_init(ctx, rho0, ux0, uy0, adj0, drho0, n):
+    _check(_lib.lbm_adjoint_init(ctx, _ptr(rho0, torch.float32, n, "rho0"), _ptr(ux0, torch.float32, n, "ux0"),
+                                 _ptr(uy0, torch.float32, n, "uy0"), _bytes_ptr(adj0, 44 * n, "adj0"),
+                                 _ptr(drho0, torch.float32, n, "drho0")))
+
+
+def lbm_adjoint_theta(ctx, read=True, reset=True):
+    out = (ctypes.c_double * 3)()
+    _check(_lib.lbm_adjoint_theta(ctx, out if read else None, 1 if reset else 0))
+    return tuple(out) if read else None
+
+
+def lbm_param_jacobian(params: lbm_params):
+    """d(G'^2, K', RT)/d(sigma, W, T_r) as a 3 x 3 nested list (rows: theta)."""
+    out = (ctypes.c_double * 9)()
+    _check(_lib.lbm_param_jacobian(ctypes.byref(params), out))
+    return [list(out[3 * k:3 * k + 3]) for k in range(3)]
+
+
 def lbm_time(ctx) -> int:
     return int(_lib.lbm_time(ctx))
 
@@ -241,6 +313,57 @@ class Lattice:
             tot = lbm_moments(self.ctx, rho, ux, uy, True, n=self.n)
             return rho, ux, uy, tot
         return lbm_moments(self.ctx, None, None, None, True, n=self.n)
+
+    # ---- checkpoints -------------------------------------------------------
+    def checkpoint_buffer(self):
+        return torch.empty(lbm_checkpoint_bytes(self.params), dtype=torch.uint8, device=self.f_a.device)
+
+    def save_state(self, dst=None):
+        dst = self.checkpoint_buffer() if dst is None else dst
+        lbm_save_state(self.ctx, dst, lbm_checkpoint_bytes(self.params))
+        return dst
+
+    def load_state(self, src, t=0):
+        lbm_load_state(self.ctx, src, t, lbm_checkpoint_bytes(self.params))
+        self._keep = [src]
+        return self
+
+    def step_saved(self, src, dst):
+        lbm_step_saved(self.ctx, src, dst, lbm_checkpoint_bytes(self.params))
+        return dst
+
+    # ---- adjoint -----------------------------------------------------------
+    def adjoint_buffer(self):
+        nbytes = lbm_adjoint_bytes(self.params)
+        if nbytes == 0:
+            raise LbmError(LBM_EINVAL, "the adjoint needs LBM_FP32 storage")
+        return torch.empty(nbytes, dtype=torch.uint8, device=self.f_a.device)
+
+    def adjoint_seed(self, lam, adj=None):
+        adj = self.adjoint_buffer() if adj is None else adj
+        lam = torch.as_tensor(lam, dtype=torch.float32).to(self.f_a.device).contiguous()
+        lbm_adjoint_seed(self.ctx, lam, adj, self.n)
+        return adj
+
+    def adjoint_step(self, f_t, adj_next, adj_out):
+        lbm_adjoint_step(self.ctx, f_t, adj_next, adj_out, self.n, lbm_checkpoint_bytes(self.params))
+        return adj_out
+
+    def adjoint_get(self, adj):
+        lam = torch.empty((9, self.ny, self.nx), dtype=torch.float32, device=self.f_a.device)
+        lbm_adjoint_get(self.ctx, adj, lam, self.n)
+        return lam
+
+    def adjoint_init(self, rho0, adj0, ux0=None, uy0=None):
+        dev = self.f_a.device
+        conv = lambda a: None if a is None else torch.as_tensor(a, dtype=torch.float32).to(dev).contiguous()
+        rho0, ux0, uy0 = conv(rho0), conv(ux0), conv(uy0)
+        drho0 = torch.empty((self.ny, self.nx), dtype=torch.float32, device=dev)
+        lbm_adjoint_init(self.ctx, rho0, ux0, uy0, adj0, drho0, self.n)
+        return drho0
+
+    def adjoint_theta(self, reset=True):
+        return lbm_adjoint_theta(self.ctx, True, reset)
 
     @property
     def time(self):

@@ -1,0 +1,132 @@
+"""Checkpointed forward and adjoint of a rollout, and its torch.autograd.Function.
+
+The map differentiated is
+
+    rho0 --lbm_init--> f(0) = f^eq(rho0, u0, eta(rho0))  (zero u0 unless given)
+         --n x lbm_step--> f(n) --> rho_T = sum_i f_i(n),
+
+with the parameters sigma, W and T_r entering through theta = (G'^2, K', R T)
+of the self-tuning EOS (main Eqs. 20-23).
+
+Forward: the library state is saved every ``every`` steps (lbm_save_state).
+Backward: from the last segment to the first, the segment's states are
+recomputed from its checkpoint with lbm_step_saved (the same kernel as
+lbm_step, so bit for bit the forward's states) and the adjoint steps run back
+through them; lbm_adjoint_init closes with dL/d rho0, and
+
+    dL/d(sigma, W, T_r) = J^T dL/d theta,   J = lbm_param_jacobian.
+
+Device memory: ceil(n / every) checkpoints + (every - 1) segment states + two
+adjoint states (11 planes each), all FP32 over nx*ny nodes.  Every step of
+the path runs in the HIP library; this module only orders the calls.
+"""
+from __future__ import annotations
+
+import torch
+
+from .lbm import Lattice, lbm_adjoint_theta, lbm_param_jacobian
+
+
+class Rollout:
+    """Forward rollout with checkpoints, then one adjoint sweep."""
+
+    def __init__(self, nx, ny, nsteps, every=100, device="cuda", **kw):
+        if kw.get("storage", "fp32") not in ("fp32", 0):
+            raise ValueError("the adjoint is defined for FP32 storage only")
+        if nsteps < 0 or every < 1:
+            raise ValueError("nsteps >= 0 and every >= 1 are required")
+        self.lat = Lattice(nx, ny, device=device, **kw)
+        self.nx, self.ny, self.nsteps, self.every = nx, ny, int(nsteps), int(every)
+        self.starts = list(range(0, self.nsteps, self.every))
+        self.ckpt = [None] * len(self.starts)
+        self.pool = []  # segment states beyond the checkpoint
+        self.inputs = None
+
+    def _conv(self, a):
+        if a is None:
+            return None
+        return torch.as_tensor(a).to(device=self.lat.f_a.device, dtype=torch.float32).reshape(
+            self.ny, self.nx).contiguous()
+
+    def forward(self, rho0, ux0=None, uy0=None):
+        """rho_T (ny, nx) float32 after nsteps steps from f^eq(rho0)."""
+        lat = self.lat
+        self.inputs = (self._conv(rho0), self._conv(ux0), self._conv(uy0))
+        lat.init(*self.inputs)
+        for s, t0 in enumerate(self.starts):
+            self.ckpt[s] = lat.save_state(self.ckpt[s])
+            lat.step(min(self.every, self.nsteps - t0))
+        return lat.moments()[0]
+
+    def _segment_states(self, s):
+        """States of times t0 .. t0 + m - 1 of segment s, recomputed."""
+        m = min(self.every, self.nsteps - self.starts[s])
+        while len(self.pool) < m - 1:
+            self.pool.append(self.lat.checkpoint_buffer())
+        states = [self.ckpt[s]] + self.pool[:m - 1]
+        for j in range(m - 1):
+            self.lat.step_saved(states[j], states[j + 1])
+        return states
+
+    def backward_state(self, lam_T):
+        """Adjoint of f(0) (an adjoint-state buffer) for Lambda(T) = lam_T
+        (9, ny, nx); leaves dL/d theta of the steps in the accumulator."""
+        lat = self.lat
+        lbm_adjoint_theta(lat.ctx, read=False, reset=True)
+        adj = [lat.adjoint_seed(lam_T), lat.adjoint_buffer()]
+        for s in reversed(range(len(self.starts))):
+            states = self._segment_states(s)
+            for f_t in reversed(states):
+                lat.adjoint_step(f_t, adj[0], adj[1])
+                adj.reverse()
+        return adj[0]
+
+    def backward(self, grad_rho_T):
+        """(dL/d rho0 (ny, nx) float32, dL/d theta (3,), dL/d(sigma, W, T_r) (3,))
+        for dL/d rho_T = grad_rho_T."""
+        if self.inputs is None:
+            raise RuntimeError("backward before forward")
+        g = self._conv(grad_rho_T)
+        adj0 = self.backward_state(g.expand(9, self.ny, self.nx).contiguous())
+        rho0, ux0, uy0 = self.inputs
+        drho0 = self.lat.adjoint_init(rho0, adj0, ux0, uy0)
+        dth = self.lat.adjoint_theta(reset=True)
+        J = lbm_param_jacobian(self.lat.params)
+        dp = tuple(sum(J[k][j] * dth[k] for k in range(3)) for j in range(3))
+        return drho0, dth, dp
+
+    def release(self):
+        self.ckpt = [None] * len(self.starts)
+        self.pool = []
+        self.lat.close()
+
+
+class LBMRollout(torch.autograd.Function):
+    """rho_T = LBMRollout.apply(rho0, sigma, width, tr, nsteps, every, options).
+
+    rho0 is an (ny, nx) CUDA tensor; sigma, width and tr are Python floats
+    or scalar tensors (gradients are returned for tensors); options is a dict
+    of further make_params keywords (s_p, varpi, ...) or None."""
+
+    @staticmethod
+    def forward(ctx, rho0, sigma, width, tr, nsteps, every, options):
+        ny, nx = rho0.shape
+        r = Rollout(nx, ny, int(nsteps), int(every), device=rho0.device, sigma=float(sigma), width=float(width),
+                    tr=float(tr), **dict(options or {}))
+        out = r.forward(rho0.detach())
+        ctx.rollout = r
+        ctx.rho_dtype = rho0.dtype
+        ctx.meta = [(p.dtype, p.device) if torch.is_tensor(p) else None for p in (sigma, width, tr)]
+        return out
+
+    @staticmethod
+    def backward(ctx, grad):
+        drho0, _, dp = ctx.rollout.backward(grad)
+        ctx.rollout.release()
+        params = [None if m is None else torch.tensor(v, dtype=m[0], device=m[1]) for m, v in zip(ctx.meta, dp)]
+        return (drho0.to(ctx.rho_dtype), *params, None, None, None)
+
+
+def lbm_rollout(rho0, sigma, width, tr, nsteps, every=100, **options):
+    """Differentiable rho_T of an nsteps rollout from f^eq(rho0)."""
+    return LBMRollout.apply(rho0, sigma, width, tr, nsteps, every, options)

@@ -80,3 +80,42 @@ def test_buffer_sizes():
 def test_null_context_rejected():
     assert L._lib.lbm_step(None, 1) == L.LBM_EINVAL
     assert L._lib.lbm_time(None) == -1
+
+
+def test_checkpoint_and_adjoint_sizes():
+    p = pkg.make_params(100, 30)
+    assert pkg.lbm_checkpoint_bytes(p) == 9 * 100 * 30 * 4
+    assert pkg.lbm_adjoint_bytes(p) == 11 * 100 * 30 * 4
+    p16 = pkg.make_params(100, 30, storage="bf16")
+    assert pkg.lbm_checkpoint_bytes(p16) == 9 * 100 * 30 * 2 + 100 * 30 * 2
+    assert pkg.lbm_adjoint_bytes(p16) == 0  # the adjoint is FP32-only
+    assert pkg.lbm_checkpoint_bytes(pkg.make_params(0, 3)) == 0
+
+
+def test_adjoint_calls_without_context_rejected():
+    assert L._lib.lbm_adjoint_step(None, None, None, None) == L.LBM_EINVAL
+    assert L._lib.lbm_adjoint_theta(None, None, 1) == L.LBM_EINVAL
+    assert L._lib.lbm_save_state(None, None) == L.LBM_EINVAL
+
+
+@pytest.mark.parametrize("tr,width,sigma", [(0.8, 10.0, None), (0.7, 10.0, 1.8e-3), (0.6, 14.0, 3e-3)])
+def test_param_jacobian_against_oracle_map(tr, width, sigma):
+    """d(G'^2, K', RT)/d(sigma, W, T_r) of the library against central
+    differences of the oracle's own parameter map (FP64)."""
+    p = pkg.make_params(16, 16, tr=tr, width=width, sigma=sigma or 0.0)
+    jac = pkg.lbm_param_jacobian(p)
+    s0 = pkg.lbm_derive(p).sigma  # the sigma the context uses, held independent
+
+    def theta(s, w, t):
+        co = hm.derive(hm.Params(tr=t, width=w, sigma=s))
+        return [co.G2, co.Kp, co.RT]
+
+    x0 = [s0, width, tr]
+    for j in range(3):
+        h = 1e-4 * x0[j]
+        xp, xm = list(x0), list(x0)
+        xp[j] += h
+        xm[j] -= h
+        num = [(a - b) / (2 * h) for a, b in zip(theta(*xp), theta(*xm))]
+        for k in range(3):
+            assert jac[k][j] == pytest.approx(num[k], rel=1e-6, abs=1e-12), (k, j)

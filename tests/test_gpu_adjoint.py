@@ -1,0 +1,228 @@
+"""The HIP adjoint against the oracle's exact derivatives (complex step,
+FP64) and the oracle's finite differences: one adjoint step, the adjoint of
+the initial equilibrium, a checkpointed rollout gradient with respect to
+rho0 and (G'^2, K', R T) and (sigma, W, T_r), and the torch autograd
+wrapper.  Calls go through the C ABI.
+
+Tolerances.  The adjoint runs in FP32.  Per element, lambda^t is a sum of a
+few dozen products of O(1) factors, so its rounding is a few ulps of the
+largest term: bound 1e-5 of max |lambda| (about 80 ulps).  Parameter sums
+are FP64 sums of FP32 node terms: bound 1e-5 of the sum of |terms|, with
+the terms taken from the oracle.  Rollout gradients carry the FP32 forward
+(relative state error ~1e-6) through the loss: bound 1e-4 relative."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1809_02390_amd as pkg
+import workloads as wl
+from oracle import adjoint as adj
+from oracle import hostmap as hm
+from oracle import lbm
+from tests._gpu_helpers import oracle_init, params_pair
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def f32(a):
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+def nonequilibrium_state(nx, ny, co, seed):
+    """A droplet with a velocity field, advanced 3 oracle steps, in float32."""
+    rng = np.random.default_rng(seed)
+    rho = wl.droplets(nx, ny, co.rho_g, co.rho_l, co.width, [(nx / 2, ny / 2)], [min(nx, ny) / 4])
+    ux, uy = rng.uniform(-0.03, 0.03, (2, ny, nx))
+    return f32(lbm.run(oracle_init(co, rho, ux, uy), co, 3))
+
+
+def param_term_scale(f, lam, co):
+    """sum |lam . d step / d theta_k| per node and population (the scale of
+    the FP32 terms the device sums), k = 0..2."""
+    th = np.array(adj.theta_of(co), dtype=np.complex128)
+    out = []
+    for k in range(3):
+        t = th.copy()
+        t[k] += 1j * adj.H
+        jd = np.imag(lbm.step(f.astype(np.complex128), adj._with_theta(co, t))) / adj.H
+        out.append(np.abs(lam * jd).sum())
+    return np.array(out)
+
+
+@pytest.fixture(scope="module")
+def case():
+    nx, ny = 40, 30
+    _, co = params_pair(nx, ny, tr=0.7, width=5.0)
+    f = nonequilibrium_state(nx, ny, co, 5)
+    lam = f32(np.random.default_rng(6).standard_normal(f.shape))
+    return nx, ny, co, f, lam
+
+
+def test_seed_and_get_roundtrip(case):
+    nx, ny, co, f, lam = case
+    lat = pkg.Lattice(nx, ny, tr=0.7, width=5.0)
+    a = lat.adjoint_seed(lam)
+    got = lat.adjoint_get(a).cpu().numpy()
+    assert np.array_equal(got, lam.astype(np.float32))
+
+
+def test_adjoint_step_matches_oracle(case):
+    nx, ny, co, f, lam = case
+    lat = pkg.Lattice(nx, ny, tr=0.7, width=5.0).set_state(f)
+    ck = lat.save_state()
+    a, b = lat.adjoint_seed(lam), lat.adjoint_buffer()
+    lat.adjoint_theta(reset=True)
+    lat.adjoint_step(ck, a, b)
+    got = lat.adjoint_get(b).double().cpu().numpy()
+    ref = adj.step_vjp(f, lam, co)
+    assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
+    dth = np.array(lat.adjoint_theta(reset=True))
+    ref_th = adj.step_param_vjp(f, lam, co)
+    scale = param_term_scale(f, lam, co)
+    assert np.all(np.abs(dth - ref_th) <= 1e-5 * scale), (dth, ref_th, scale)
+
+
+def test_two_adjoint_steps_match_oracle(case):
+    """The second step reads a nonzero stencil adjoint (the scatter of the
+    force terms to the neighbour densities)."""
+    nx, ny, co, f, lam = case
+    lat = pkg.Lattice(nx, ny, tr=0.7, width=5.0).set_state(f)
+    ck0 = lat.save_state()
+    lat.step(1)
+    ck1 = lat.save_state()
+    f1 = lat.state().double().cpu().numpy()
+    a, b = lat.adjoint_seed(lam), lat.adjoint_buffer()
+    lat.adjoint_step(ck1, a, b)
+    lat.adjoint_step(ck0, b, a)
+    got = lat.adjoint_get(a).double().cpu().numpy()
+    ref = adj.step_vjp(f, adj.step_vjp(f1, lam, co), co)
+    assert np.abs(got - ref).max() <= 2e-5 * np.abs(ref).max()
+
+
+def test_adjoint_init_matches_oracle(case):
+    nx, ny, co, f, lam = case
+    rho0 = f32(f.sum(0))
+    rng = np.random.default_rng(8)
+    ux0, uy0 = f32(rng.uniform(-0.02, 0.02, (2, ny, nx)))
+    lat = pkg.Lattice(nx, ny, tr=0.7, width=5.0)
+    a = lat.adjoint_seed(lam)
+    lat.adjoint_theta(reset=True)
+    for u in ((None, None), (ux0, uy0)):
+        got = lat.adjoint_init(rho0, a, *u).double().cpu().numpy()
+        dth = np.array(lat.adjoint_theta(reset=True))
+        rho_c = rho0 + 0j
+        ref_g = np.imag(lbm.equilibrium(rho_c + 1j * adj.H, co, *(None if v is None else v for v in u)))
+        ref_g = (lam * ref_g).sum(0) / adj.H
+        assert np.abs(got - ref_g).max() <= 1e-5 * np.abs(ref_g).max()
+        if u[0] is None:
+            _, ref_th = adj.equilibrium_vjp(rho0, lam, co)
+            assert np.allclose(dth, ref_th, rtol=1e-5, atol=0), (dth, ref_th)
+
+
+def test_step_saved_is_bitwise_lbm_step():
+    nx, ny = 70, 37
+    _, co = params_pair(nx, ny, tr=0.8)
+    rho = wl.droplets(nx, ny, co.rho_g, co.rho_l, co.width, [(30, 20)], [11.0])
+    lat = pkg.Lattice(nx, ny, tr=0.8).init(rho)
+    bufs = [lat.save_state(), lat.checkpoint_buffer(), lat.checkpoint_buffer()]
+    for k in range(5):
+        lat.step_saved(bufs[k % 2], bufs[(k + 1) % 2])
+    lat.step(5)
+    lat.save_state(bufs[2])
+    assert torch.equal(bufs[1], bufs[2])
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
+def test_load_state_repeats_the_run(storage):
+    nx, ny = 70, 37
+    _, co = params_pair(nx, ny, tr=0.8)
+    rho = wl.droplets(nx, ny, co.rho_g, co.rho_l, co.width, [(30, 20)], [11.0])
+    lat = pkg.Lattice(nx, ny, tr=0.8, storage=storage).init(rho)
+    lat.step(3)
+    ck = lat.save_state()
+    lat.step(7)
+    a = lat.state().clone()
+    lat.load_state(ck, 3)
+    assert lat.time == 3
+    lat.step(7)
+    assert torch.equal(a, lat.state()) and lat.time == 10
+
+
+# ---------------------------------------------------------------------------
+# Checkpointed rollout gradient
+# ---------------------------------------------------------------------------
+ROLL = dict(nx=64, ny=48, nsteps=40, every=7, tr=0.8, width=6.0)
+
+
+@pytest.fixture(scope="module")
+def rollout_case():
+    nx, ny = ROLL["nx"], ROLL["ny"]
+    p, co = params_pair(nx, ny, tr=ROLL["tr"], width=ROLL["width"])
+    rho0 = wl.droplets(nx, ny, co.rho_g, co.rho_l, co.width, [(30, 22)], [12.0])
+    target = wl.ellipse(nx, ny, co.rho_g, co.rho_l, co.width, (nx / 2, ny / 2), 15.0, 9.6)
+    r = pkg.Rollout(nx, ny, ROLL["nsteps"], ROLL["every"], tr=ROLL["tr"], width=ROLL["width"])
+    rho_T = r.forward(rho0).double().cpu().numpy()
+    drho0, dth, dp = r.backward(torch.tensor(2 * (rho_T - target)))
+    return co, rho0, target, rho_T, drho0.double().cpu().numpy(), np.array(dth), np.array(dp)
+
+
+def test_rollout_forward_matches_oracle(rollout_case):
+    co, rho0, target, rho_T, *_ = rollout_case
+    ref = adj.rollout(rho0, co, ROLL["nsteps"]).sum(0)
+    assert np.abs(rho_T - ref).max() <= 1e-5 * co.rho_l
+
+
+def test_rollout_gradient_rho0_matches_complex_step(rollout_case):
+    co, rho0, target, rho_T, drho0, dth, dp = rollout_case
+    for d in wl.random_directions(rho0.shape, 3, seed=11):
+        exact = adj.loss_directional(rho0, co, ROLL["nsteps"], target, drho0=d)
+        assert (drho0 * d).sum() == pytest.approx(exact, rel=1e-4)
+
+
+def test_rollout_gradient_theta_matches_complex_step(rollout_case):
+    co, rho0, target, rho_T, drho0, dth, dp = rollout_case
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = 1.0
+        exact = adj.loss_directional(rho0, co, ROLL["nsteps"], target, dtheta=e)
+        assert dth[k] == pytest.approx(exact, rel=1e-4), k
+
+
+def test_rollout_gradient_params_match_finite_differences(rollout_case):
+    """dL/d(sigma, W, T_r) against FP64 central differences of the oracle
+    rollout with the oracle's own parameter map."""
+    co, rho0, target, rho_T, drho0, dth, dp = rollout_case
+    x0 = [co.sigma, ROLL["width"], ROLL["tr"]]
+
+    def L(x):
+        c = hm.derive(hm.Params(sigma=x[0], width=x[1], tr=x[2]))
+        return adj.loss(rho0, c, ROLL["nsteps"], target)
+
+    for j in range(3):
+        h = 1e-5 * x0[j]
+        xp, xm = list(x0), list(x0)
+        xp[j] += h
+        xm[j] -= h
+        num = (L(xp) - L(xm)) / (2 * h)
+        assert dp[j] == pytest.approx(num, rel=1e-4), j
+
+
+def test_autograd_function_matches_driver_and_is_deterministic(rollout_case):
+    co, rho0, target, rho_T, drho0, dth, dp = rollout_case
+    tgt = torch.tensor(target, device=DEV)
+
+    def grads():
+        r0 = torch.tensor(rho0, dtype=torch.float32, device=DEV, requires_grad=True)
+        s = torch.tensor(co.sigma, dtype=torch.float64, requires_grad=True)
+        w = torch.tensor(ROLL["width"], dtype=torch.float64, requires_grad=True)
+        t = torch.tensor(ROLL["tr"], dtype=torch.float64, requires_grad=True)
+        out = pkg.lbm_rollout(r0, s, w, t, ROLL["nsteps"], every=ROLL["every"])
+        ((out.double() - tgt) ** 2).sum().backward()
+        return r0.grad.clone(), torch.stack([s.grad, w.grad, t.grad])
+
+    g1, p1 = grads()
+    g2, p2 = grads()
+    assert torch.equal(g1, g2) and torch.equal(p1, p2)
+    np.testing.assert_allclose(g1.double().cpu().numpy(), drho0, rtol=0, atol=1e-6 * np.abs(drho0).max())
+    np.testing.assert_allclose(p1.numpy(), dp, rtol=1e-6)
