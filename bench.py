@@ -1,15 +1,25 @@
 #!/usr/bin/env python3
-"""Benchmark of the self-tuning-EOS D2Q9 step on one MI355X.
+"""Benchmark of the self-tuning-EOS D2Q9 path on one MI355X.
 
-Workload: spinodal decomposition on a periodic 4096 x 4096 lattice at
-T/T_c = 0.7 (mean of the coexistence densities plus seeded uniform noise
+Headline workload: spinodal decomposition on a periodic 4096 x 4096 lattice
+at T/T_c = 0.7 (mean of the coexistence densities plus seeded uniform noise
 +-0.01), W = 10, sigma from the paper's sound-speed rule.  A step is one
 fused launch (density halo, force, collision, streaming).  Inputs are
-resident in HBM before the timed region starts.
+resident in HBM before any timed region starts; every timed region is
+bracketed by HIP events on the stream the kernels are launched on.
 
-Prints one JSON line: MLUPS of the FP32 step, its HBM roofline fraction
-(72 algorithmic bytes per lattice update), and the FP64 CPU oracle timed on
-a bounded crop of the same workload.
+Prints one JSON line:
+  value / roofline   MLUPS of the FP32 step and its HBM roofline fraction
+                     (72 algorithmic bytes per lattice update);
+  legs.fp16, .bf16   the same step with 2-byte storage of f (40 B/LU), the
+                     ratio to FP32, and the coexistence-density error of a
+                     relaxed flat interface against the Maxwell densities;
+  legs.fwd_adjoint   checkpointed forward + adjoint over 1000 steps of the
+                     2048^2 droplet-pair crop (T/T_c = 0.6, K = 100), the
+                     adjoint kernel's own roofline, and the gradient error of
+                     the 512^2 droplet-to-ellipse problem (2000 steps, K = 100)
+                     against exact oracle derivatives stored in tests/golden;
+  cpu_baseline       the FP64 oracle timed on a bounded crop.
 """
 from __future__ import annotations
 
@@ -25,8 +35,15 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "MLUPS + % HBM roofline, FP32 vs FP16-storage step; fwd+adjoint MLUPS at stated err"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_LU = {"fp32": 72}
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_step_f32_spinodal4096.json")
+# Algorithmic HBM bytes per lattice update (LU):
+#   step: 9 populations read + 9 written (4 B, or 2 B plus the 2-byte reference density read and written);
+#   adjoint step: f(t) 9 + L 9 + force adjoint 2 read, L 9 + force adjoint 2 written (4 B each).
+BYTES_PER_LU = {"fp32": 72, "fp16": 40, "bf16": 40}
+ADJ_BYTES_PER_LU = 124
+# rocprofv3 FETCH_SIZE / WRITE_SIZE summaries of each kernel on the 4096^2 workload
+PROFILE_TRAFFIC = {k: os.path.join(ROOT, "profiles", f"traffic_{k}_spinodal4096.json")
+                   for k in ("step_f32", "step_f16", "step_bf16", "adjoint_f32")}
+GOLDEN = os.path.join(ROOT, "tests", "golden", "droplet512_gradients.json")
 
 
 def kernel_source_hash():
@@ -37,17 +54,155 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(n_nodes):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source; else None."""
+def measured_traffic(kernel, n_nodes):
+    """HBM bytes per launch of `kernel` on n_nodes from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source
+    and lattice size; else None."""
     try:
-        with open(PROFILE_TRAFFIC) as fh:
+        with open(PROFILE_TRAFFIC[kernel]) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
     if t.get("kernel_sha") != kernel_source_hash() or t.get("n_nodes") != n_nodes:
         return None
-    return t.get("bytes_per_launch")
+    return round(t["bytes_per_launch"])
+
+
+class Timer:
+    """HIP events on torch's current stream (the stream the library uses)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.stream = torch.cuda.current_stream()
+
+    def __call__(self, fn):
+        torch = self.torch
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(self.stream)
+        fn()
+        b.record(self.stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)  # ms
+
+
+def step_leg(pkg, wl, timer, storage, n, steps, warmup, tr=0.7, width=10.0):
+    d = pkg.lbm_derive(pkg.make_params(n, n, tr=tr, width=width))
+    rho0 = wl.spinodal({"rho_g": d.rho_g, "rho_l": d.rho_l, "width": width}, n=n)
+    lat = pkg.Lattice(n, n, tr=tr, width=width, storage=storage).init(rho0)
+    lat.step(warmup)
+    ms = timer(lambda: lat.step(steps))
+    tot = lat.moments(fields=False)
+    lat.close()
+    if not all(np.isfinite(tot)):
+        raise RuntimeError(f"{storage} state diverged")
+    per = ms / steps
+    gbs = BYTES_PER_LU[storage] * n * n / (per * 1e-3) / 1e9
+    return d, rho0, {"mlups": round(n * n * steps / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(per, 5),
+                     "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "algorithmic_bytes_per_lu": BYTES_PER_LU[storage],
+                     "traffic": measured_traffic("step_" + storage.replace("fp", "f"), n * n)}
+
+
+def coexistence_leg(pkg, wl, storage, tr=0.7, width=10.0, ny=128, steps=20000):
+    """Flat interface relaxed for `steps` steps: bulk densities against the
+    Maxwell construction of the library's host map, |d rho| / rho_l."""
+    d = pkg.lbm_derive(pkg.make_params(4, ny, tr=tr, width=width))
+    rho0 = wl.flat_slab(4, ny, d.rho_g, d.rho_l, width / wl.TANH_WIDTH_FACTOR)
+    lat = pkg.Lattice(4, ny, tr=tr, width=width, storage=storage).init(rho0).step(steps)
+    rho = lat.moments()[0].double().mean(1).cpu().numpy()
+    lat.close()
+    liq, gas = rho[0], rho[ny // 2]  # plateau centres, ny/4 from the interfaces
+    return {"rho_l_err": float(abs(liq - d.rho_l) / d.rho_l), "rho_g_err": float(abs(gas - d.rho_g) / d.rho_l),
+            "rho_g_err_rel_rho_g": float(abs(gas - d.rho_g) / d.rho_g), "steps": steps, "lattice": f"4x{ny}"}
+
+
+def fwd_adjoint_leg(pkg, wl, timer, torch, n=2048, steps=1000, every=100):
+    """Checkpointed forward + adjoint of the droplet-pair crop, whole job."""
+    tr, width = 0.6, 10.0
+    d = pkg.lbm_derive(pkg.make_params(n, n, tr=tr, width=width))
+    rho0 = wl.coalescence({"rho_g": d.rho_g, "rho_l": d.rho_l, "width": width}, nx=n, ny=n)
+    r = pkg.Rollout(n, n, steps, every, tr=tr, width=width)
+    t_f = timer(lambda: r.forward(rho0))
+    rho_T = r.lat.moments()[0]
+    grad = 2.0 * (rho_T - torch.tensor(rho0, dtype=torch.float32, device="cuda"))
+    out = {}
+    t_b = timer(lambda: out.update(zip(("drho0", "dth", "dp"), r.backward(grad))))
+    r.release()
+    if not np.all(np.isfinite(out["dth"])):
+        raise RuntimeError("adjoint diverged")
+    return {"workload": f"droplet pair R=400, gap 20, {n}x{n} crop, T/Tc={tr}, W={width}",
+            "steps": steps, "checkpoint_every": every,
+            "mlups": round(n * n * steps / ((t_f + t_b) * 1e-3) / 1e6, 1),
+            "ms_forward": round(t_f, 3), "ms_backward": round(t_b, 3)}
+
+
+def adjoint_kernel_leg(pkg, wl, timer, torch, n=4096, reps=200, tr=0.7, width=10.0):
+    """The adjoint step kernel alone on the 4096^2 spinodal workload (one
+    forward checkpoint, alternating adjoint buffers)."""
+    d = pkg.lbm_derive(pkg.make_params(n, n, tr=tr, width=width))
+    rho0 = wl.spinodal({"rho_g": d.rho_g, "rho_l": d.rho_l, "width": width}, n=n)
+    lat = pkg.Lattice(n, n, tr=tr, width=width).init(rho0).step(5)
+    ck = lat.save_state()
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    a = lat.adjoint_seed(torch.randn((9, n, n), device="cuda", generator=gen))
+    b = lat.adjoint_buffer()
+
+    def loop():
+        x, y = a, b
+        for _ in range(reps):
+            lat.adjoint_step(ck, x, y)
+            x, y = y, x
+
+    loop()  # warm
+    ms = timer(loop) / reps
+    th = lat.adjoint_theta(reset=True)
+    lat.close()
+    if not np.all(np.isfinite(th)):
+        raise RuntimeError("adjoint diverged")
+    gbs = ADJ_BYTES_PER_LU * n * n / (ms * 1e-3) / 1e9
+    return {"workload": f"spinodal decomposition {n}x{n}, T/Tc={tr}, W={width}", "ms_per_step": round(ms, 5),
+            "mlups": round(n * n / (ms * 1e-3) / 1e6, 1), "achieved_gbs": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_lu": ADJ_BYTES_PER_LU,
+            "traffic": measured_traffic("adjoint_f32", n * n)}
+
+
+def gradient_error(pkg, wl, timer, torch):
+    """Relative error of the fwd+adjoint directional derivatives of the 512^2
+    droplet-to-ellipse loss against the stored exact values."""
+    try:
+        with open(GOLDEN) as fh:
+            g = json.load(fh)
+    except (OSError, ValueError):
+        return {"error": "golden values missing"}
+    n, steps, tr, width, sigma = g["n"], g["nsteps"], g["tr"], g["width"], g["sigma"]
+    d = pkg.lbm_derive(pkg.make_params(n, n, tr=tr, width=width, sigma=sigma))
+    rho0 = wl.droplets(n, n, d.rho_g, d.rho_l, width, [(n / 2, n / 2)], [g["radius"]])
+    target = wl.ellipse(n, n, d.rho_g, d.rho_l, width, (n / 2, n / 2), *g["semi_axes"])
+    r = pkg.Rollout(n, n, steps, 100, tr=tr, width=width, sigma=sigma)
+    res = {}
+
+    def run():
+        rho_T = r.forward(rho0).double()
+        res["loss"] = float(((rho_T - torch.tensor(target, device="cuda")) ** 2).sum())
+        res.update(zip(("drho0", "dth", "dp"), r.backward(2.0 * (rho_T - torch.tensor(target, device="cuda")))))
+
+    ms = timer(run)
+    r.release()
+    drho0 = res["drho0"].double().cpu().numpy()
+    errs = {}
+    for name, e in g["directions"].items():
+        seed = int(name[4:]) if name.startswith("seed") else None
+        v = float(np.dot(res["dp"], e["param"]))
+        if e["rho0"]:
+            rng = np.random.default_rng(seed)
+            v += float((drho0 * rng.standard_normal((n, n)) * (d.rho_l - d.rho_g) / n).sum())
+        errs[name] = abs(v - e["value"]) / abs(e["value"])
+    return {"workload": f"droplet R={g['radius']:g} -> ellipse {g['semi_axes']}, {n}x{n}, T/Tc={tr}, "
+                        f"{steps} steps, K=100",
+            "max_rel_err": max(errs.values()), "per_direction": errs,
+            "loss_rel_err": abs(res["loss"] - g["loss"]) / g["loss"], "ms_fwd_adj": round(ms, 2),
+            "mlups": round(n * n * steps / (ms * 1e-3) / 1e6, 1)}
 
 
 def cpu_baseline(rho_full, tr, width, crop=384, budget_s=20.0):
@@ -79,6 +234,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--n", type=int, default=4096, help="lattice side (default: the 4096^2 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-fp32", action="store_true", help="skip the 2-byte and adjoint legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -90,43 +246,31 @@ def main():
     import paper_1809_02390_amd as pkg
     import workloads as wl
 
+    timer = Timer(torch)
     tr, width, n = 0.7, 10.0, args.n
-    derived = pkg.lbm_derive(pkg.make_params(n, n, tr=tr, width=width))
-    rho0 = wl.spinodal({"rho_g": derived.rho_g, "rho_l": derived.rho_l, "width": width}, n=n)
-    lat = pkg.Lattice(n, n, tr=tr, width=width)
-    lat.init(rho0)
-    torch.cuda.synchronize()
-    lat.step(args.warmup)
-    torch.cuda.synchronize()
-
-    stream = torch.cuda.current_stream()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t_wall = time.perf_counter()
-    start.record(stream)
-    lat.step(args.steps)
-    stop.record(stream)
-    torch.cuda.synchronize()
+    derived, rho0, fp32 = step_leg(pkg, wl, timer, "fp32", n, args.steps, args.warmup, tr, width)
     t_wall = time.perf_counter() - t_wall
-    ms = start.elapsed_time(stop)
-    ms_per_step = ms / args.steps
-    n_nodes = n * n
-    mlups = n_nodes * args.steps / (ms * 1e-3) / 1e6
-    tot = lat.moments(fields=False)
-    if not all(np.isfinite(tot)):
-        print("bench.py: state diverged", file=sys.stderr)
-        sys.exit(1)
+    legs = {}
+    if not args.only_fp32:
+        for st in ("fp16", "bf16"):
+            _, _, leg = step_leg(pkg, wl, timer, st, n, args.steps, args.warmup, tr, width)
+            leg["ratio_vs_fp32"] = round(leg["mlups"] / fp32["mlups"], 4)
+            leg["coexistence"] = coexistence_leg(pkg, wl, st)
+            legs[st] = leg
+        legs["fp32_coexistence"] = coexistence_leg(pkg, wl, "fp32")
+        legs["fwd_adjoint"] = fwd_adjoint_leg(pkg, wl, timer, torch)
+        legs["fwd_adjoint"]["adjoint_kernel"] = adjoint_kernel_leg(pkg, wl, timer, torch)
+        legs["fwd_adjoint"]["gradient"] = gradient_error(pkg, wl, timer, torch)
 
-    achieved = BYTES_PER_LU["fp32"] * n_nodes / (ms_per_step * 1e-3) / 1e9
-    traffic = measured_traffic(n_nodes)
     out = {
         "metric": METRIC,
-        "value": round(mlups, 1),
+        "value": fp32["mlups"],
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
+        "ms_per_step": fp32["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -134,10 +278,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"spinodal decomposition {n}x{n}, T/Tc={tr}, W={width}, "
                                f"sigma={derived.sigma:.6g}", "nx": n, "ny": n, "storage": "fp32"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "step_f32", "algorithmic_bytes_per_lu": BYTES_PER_LU["fp32"]},
-        "wall_s_timed": round(t_wall, 3),
+        "roofline": {"bound": "hbm", "achieved": fp32["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": fp32["frac"], "traffic": fp32["traffic"], "kernel": "step_kernel<F32>",
+                     "algorithmic_bytes_per_lu": BYTES_PER_LU["fp32"]},
+        "legs": legs,
+        "wall_s_fp32_leg": round(t_wall, 3),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(rho0, tr, width)

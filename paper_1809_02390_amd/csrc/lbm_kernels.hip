@@ -89,9 +89,18 @@ struct Store16 {
 // ---------------------------------------------------------------------------
 // Addressing: per-plane base pointers (uniform) and 32-bit byte offsets
 // ---------------------------------------------------------------------------
+// i mod n.  Tile coordinates lie within one period of [0, n) except on
+// lattices narrower than a tile, which alone take the integer division.
 __device__ __forceinline__ int wrap(int i, int n) {
-  i %= n;
-  return i < 0 ? i + n : i;
+  if (i >= n)
+    i -= n;
+  else if (i < 0)
+    i += n;
+  if ((unsigned)i >= (unsigned)n) {
+    i %= n;
+    if (i < 0) i += n;
+  }
+  return i;
 }
 
 // Row offsets (row * nx * ES) of rows y, y-1, y+1 and column offsets
@@ -101,13 +110,14 @@ struct NodeAddr {
   unsigned r0, rm, rp, c0, cm, cp;
 };
 
+// One multiplication per node; the neighbours' offsets are the node's plus
+// or minus one row (column), or the opposite edge.
 template <int ES>
 __device__ __forceinline__ NodeAddr<ES> node_addr(int x, int y, int nx, int ny) {
-  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-  const unsigned rb = ES * (unsigned)nx;
-  return {rb * (unsigned)y, rb * (unsigned)ym, rb * (unsigned)yp, ES * (unsigned)x, ES * (unsigned)xm,
-          ES * (unsigned)xp};
+  const unsigned rb = ES * (unsigned)nx, r0 = rb * (unsigned)y, rlast = rb * (unsigned)(ny - 1);
+  const unsigned c0 = ES * (unsigned)x, clast = ES * (unsigned)(nx - 1);
+  return {r0, y == 0 ? rlast : r0 - rb, y == ny - 1 ? 0u : r0 + rb,
+          c0, x == 0 ? clast : c0 - ES, x == nx - 1 ? 0u : c0 + ES};
 }
 
 template <typename E>

@@ -2,10 +2,13 @@
 
 Runs, on the current GPU:
   1. a plain device-to-device copy of ``--copy-mib`` MiB, ``--copies`` times
-     (torch's copy kernel: reads and writes exactly that many bytes), used to
-     calibrate the FETCH_SIZE / WRITE_SIZE counters;
-  2. ``--steps`` steps of the library's step kernel on the 4096 x 4096
-     spinodal workload (T/T_c = 0.7, W = 10) with the chosen storage.
+     (the runtime's copy kernel: reads and writes exactly that many bytes),
+     used to calibrate the FETCH_SIZE / WRITE_SIZE counters;
+  2. ``--steps`` launches of one library kernel on the 4096 x 4096 spinodal
+     workload (T/T_c = 0.7, W = 10):
+       --what step     the step kernel with the chosen --storage;
+       --what adjoint  the FP32 adjoint step (forward state of the workload,
+                       seeded adjoint, alternating adjoint buffers).
 
 Example:
     rocprofv3 --pmc FETCH_SIZE -d out -o pmc -- python -m paper_1809_02390_amd.profile_driver
@@ -24,6 +27,7 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--storage", default="fp32")
+    ap.add_argument("--what", choices=("step", "adjoint"), default="step")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--copies", type=int, default=3)
     args = ap.parse_args()
@@ -44,11 +48,24 @@ def main():
     n, tr, width = args.n, 0.7, 10.0
     d = pkg.lbm_derive(pkg.make_params(n, n, tr=tr, width=width))
     rho0 = wl.spinodal({"rho_g": d.rho_g, "rho_l": d.rho_l, "width": width}, n=n)
-    lat = pkg.Lattice(n, n, tr=tr, width=width, storage=args.storage).init(rho0)
-    lat.step(args.steps)
+    storage = args.storage if args.what == "step" else "fp32"
+    lat = pkg.Lattice(n, n, tr=tr, width=width, storage=storage).init(rho0)
+    if args.what == "step":
+        lat.step(args.steps)
+    else:
+        lat.step(5)
+        ck = lat.save_state()
+        gen = torch.Generator(device="cuda").manual_seed(0)
+        lam = torch.randn((9, n, n), device="cuda", generator=gen)
+        bufs = [lat.adjoint_seed(lam), lat.adjoint_buffer()]
+        del lam
+        for _ in range(args.steps):
+            lat.adjoint_step(ck, bufs[0], bufs[1])
+            bufs.reverse()
+        lat.adjoint_theta(reset=True)
     torch.cuda.synchronize()
-    print(f"profile_driver: copy {args.copies} x {args.copy_mib} MiB, {args.steps} steps of {n}x{n} "
-          f"({args.storage})", flush=True)
+    print(f"profile_driver: copy {args.copies} x {args.copy_mib} MiB, {args.steps} x {args.what} of {n}x{n} "
+          f"({storage})", flush=True)
 
 
 if __name__ == "__main__":
