@@ -60,7 +60,7 @@ enum lbm_status {
  * contents are internal; lbm_set_state / lbm_get_state exchange plain FP32
  * post-streaming populations in the SoA layout above. */
 enum lbm_storage {
-  LBM_FP32 = 0, /* f_i stored as float (node mass conserved exactly)    */
+  LBM_FP32 = 0, /* f_i stored as float                                  */
   LBM_FP16 = 1, /* scaled deviations in binary16                        */
   LBM_BF16 = 2  /* scaled deviations in bfloat16                        */
 };

@@ -39,6 +39,7 @@ struct Coef {
   // step (6)
   T s_e, kq2, s_eps, s_p;  // kq2 = k (s_e/2 - 1) s_eps
   T q1, q7;                // (s_e - kq2) G'^2 / 2 and s_p G'^2 / 12
+  T q2, s_q;               // s_eps G'^2 / 2 and s_q
 };
 
 // Reciprocal: the one-instruction v_rcp_f32 (1 ulp) on the device, a
@@ -52,20 +53,11 @@ __host__ __device__ __forceinline__ T recip(T x) {
   return T(1) / x;
 }
 
-// rho = sum_i f_i accumulated in FP64: for nine populations of one node the
-// double sum is exact, so every density (tile, ring, collision) is the same
-// correctly rounded value of the exact mass of the node.
-template <typename T>
-__host__ __device__ __forceinline__ double density_exact(const T* f) {
-  double s = (double)f[0];
-#pragma unroll
-  for (int i = 1; i < 9; ++i) s += (double)f[i];
-  return s;
-}
-
+// rho = sum_i f_i in one fixed order (the order forward_moments uses), so a
+// node's density is the same number in every kernel that forms it.
 template <typename T>
 __host__ __device__ __forceinline__ T density(const T* f) {
-  return (T)density_exact(f);
+  return f[0] + (((f[1] + f[3]) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8])));
 }
 
 // Stencil of main Eq. 12 (the weights 1/3 and 1/12, unit spacing):
@@ -100,7 +92,7 @@ __host__ __device__ __forceinline__ void forward_moments(const T* f, T* m) {
   const T a13 = f[1] + f[3], a24 = f[2] + f[4], d57 = f[5] + f[7], d68 = f[6] + f[8];
   const T s13 = f[1] - f[3], s24 = f[2] - f[4], e57 = f[5] - f[7], e86 = f[8] - f[6];
   const T ax = a13 + a24, dg = d57 + d68;
-  m[0] = density(f);
+  m[0] = f[0] + (ax + dg);  // = density(f)
   m[1] = T(2) * dg - ax - T(4) * f[0];
   m[2] = T(4) * f[0] - T(2) * ax + dg;
   m[3] = s13 + (e57 + e86);
@@ -111,13 +103,11 @@ __host__ __device__ __forceinline__ void forward_moments(const T* f, T* m) {
   m[8] = d57 - d68;
 }
 
-// f = M^-1 m = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m.
-// The rest population is formed last as the exact mass `mass` minus the
-// eight moving populations (FP64, exact), so the only change of the node's
-// mass is the one unbiased rounding of f_0; with the rounding of 1/9 it
-// would drift systematically.
-template <typename T, bool kExactMass = true>
-__host__ __device__ __forceinline__ void inverse_moments(const T* m, T* f, double mass) {
+// f = M^-1 m = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m,
+// with the rest population formed last as m_0 minus the eight moving ones
+// (so the populations sum to m_0 up to one rounding).
+template <typename T>
+__host__ __device__ __forceinline__ void inverse_moments(const T* m, T* f) {
   const T w0 = m[0] * T(1.0 / 9.0), w1 = m[1] * T(1.0 / 36.0), w2 = m[2] * T(1.0 / 36.0);
   const T w3 = m[3] * T(1.0 / 6.0), w4 = m[4] * T(1.0 / 12.0);
   const T w5 = m[5] * T(1.0 / 6.0), w6 = m[6] * T(1.0 / 12.0);
@@ -132,14 +122,31 @@ __host__ __device__ __forceinline__ void inverse_moments(const T* m, T* f, doubl
   f[7] = (D + w8) - (P + Q);
   f[6] = (D - w8) + (Q - P);
   f[8] = (D - w8) - (Q - P);
-  if constexpr (kExactMass) {
-    double moving = (double)f[1];
-#pragma unroll
-    for (int i = 2; i < 9; ++i) moving += (double)f[i];
-    f[0] = (T)(mass - moving);
-  } else {
-    f[0] = m[0] - (((f[1] + f[3]) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8])));
-  }
+  f[0] = m[0] - (((f[1] + f[3]) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8])));
+}
+
+// f += M^-1 dm for a moment change with dm_0 = 0 (the collision conserves
+// mass), dm_3 = Fx and dm_5 = Fy (it adds the force to the momentum).  The
+// moving rows of M sum to zero, so the nine increments sum to zero up to the
+// rounding of their additions: no constant 1/9 enters and the node's mass
+// has no systematic drift.
+template <typename T>
+__host__ __device__ __forceinline__ void add_inverse_moments(const T* dm, T Fx, T Fy, T* f) {
+  const T w1 = dm[1] * T(1.0 / 36.0), w2 = dm[2] * T(1.0 / 36.0);
+  const T w3 = Fx * T(1.0 / 6.0), w4 = dm[4] * T(1.0 / 12.0);
+  const T w5 = Fy * T(1.0 / 6.0), w6 = dm[6] * T(1.0 / 12.0);
+  const T w7 = dm[7] * T(0.25), w8 = dm[8] * T(0.25);
+  const T A = -(w1 + T(2) * w2), X = w3 - T(2) * w4, Y = w5 - T(2) * w6;
+  f[0] += T(4) * (w2 - w1);
+  f[1] += (A + w7) + X;
+  f[3] += (A + w7) - X;
+  f[2] += (A - w7) + Y;
+  f[4] += (A - w7) - Y;
+  const T D = T(2) * w1 + w2, P = w3 + w4, Q = w5 + w6;
+  f[5] += (D + w8) + (P + Q);
+  f[7] += (D + w8) - (P + Q);
+  f[6] += (D - w8) + (Q - P);
+  f[8] += (D - w8) - (Q - P);
 }
 
 // Node-local quantities at time t: velocity with the half-force correction
@@ -164,12 +171,13 @@ __host__ __device__ __forceinline__ NodeState<T> node_state(T rho, T jx, T jy, T
 }
 
 // Moment-space collision (supplement Eq. 1) by the six-step sequence of
-// supplement Sec. IV, in place on m (pre-collision moments in, post-
-// collision moments out).  g is the stencil gradient (= grad rho, supplement
+// supplement Sec. IV, as the change of the moments: dm = m-bar - m for the
+// pre-collision moments m (rows 1, 2, 4, 6, 7, 8; row 0 does not change and
+// rows 3, 5 gain Fx, Fy).  g is the stencil gradient (= grad rho, supplement
 // Eq. 61); grad p_LBE = dp_lbe g.
 template <typename T>
-__host__ __device__ __forceinline__ void collide_moments(T* m, const NodeState<T>& s, T gx, T gy,
-                                                         const Coef<T>& c) {
+__host__ __device__ __forceinline__ void collide_delta(const T* m, const NodeState<T>& s, T gx, T gy,
+                                                       const Coef<T>& c, T* dm) {
   const T rho = s.rho, ux = s.ux, uy = s.uy, Fx = s.Fx, Fy = s.Fy, dp = s.dp_lbe;
   const T ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy, u2 = ux2 + uy2, dxy = ux2 - uy2;
   // equilibrium moments m^eq (main Eq. 3) and half force moments F_m/2 (main Eq. 4)
@@ -186,8 +194,7 @@ __host__ __device__ __forceinline__ void collide_moments(T* m, const NodeState<T
   const T hF6 = T(1.5) * (Fy * ux2 + T(2) * Fx * uxy) - T(0.5) * Fy;
   const T hF7 = Fx * ux - Fy * uy;
   const T hF8 = T(0.5) * (Fx * uy + Fy * ux);
-  // (1) d = m - m^eq + F_m/2; the post-collision moment starts from
-  //     2 m^eq - m = (m^eq + F_m/2) - d
+  // (1) d = m - m^eq + F_m/2
   const T d1 = m[1] - meq1 + hF1, d2 = m[2] - meq2 + hF2, d4 = m[4] - meq4 + hF4;
   const T d6 = m[6] - meq6 + hF6, d7 = m[7] - meq7 + hF7, d8 = m[8] - meq8 + hF8;
   // (2) off-diagonal part of S, (3) diagonal relaxation: D = (1 - s/2)(d + N d)
@@ -206,31 +213,27 @@ __host__ __device__ __forceinline__ void collide_moments(T* m, const NodeState<T
   const T R81 = c.cR81 * uxy, R88 = c.cR88 * u2;
   const T v8x = uy * (uy2 + T(2) * ux2), v8y = ux * (ux2 + T(2) * uy2);
   const T corr8 = R81 * D1 + R88 * D8 + (c.cT8 + dp * c.cX8) * (v8x * gx + v8y * gy);
-  // (5) m-bar = (m^eq + F_m/2) - d + 2 D - corrections; rows 2, 4, 6 have no
-  //     coupling, so -d + 2 D = (1 - s) d there.  (6) adds S Q_m with
+  // (5) m-bar = m - 2 d + 2 F_m/2 + 2 D - corrections; rows 2, 4, 6 have no
+  //     coupling, so -2 d + 2 D = -s d there.  (6) adds S Q_m with
   //     F-tilde = G g (main Eq. 14): Q_1 = -Q_2 = G^2 |g|^2 / 2.
   const T gg = gx * gx + gy * gy;
-  m[0] = rho;
-  m[1] = (meq1 + hF1) - d1 + T(2) * D1 - corr1 + c.q1 * gg;
-  m[2] = (meq2 + hF2) + c.one_m_seps * d2 - c.s_eps * T(0.5) * c.g2 * gg;
-  m[3] = m[3] + Fx;  // momentum gains F, density unchanged
-  m[4] = (meq4 + hF4) + c.one_m_sq * d4;
-  m[5] = m[5] + Fy;
-  m[6] = (meq6 + hF6) + c.one_m_sq * d6;
-  m[7] = (meq7 + hF7) - d7 + T(2) * D7 - corr7 + c.q7 * (gx * gx - gy * gy);
-  m[8] = (meq8 + hF8) - d8 + T(2) * D8 - corr8 + c.q7 * (gx * gy);
+  dm[1] = T(2) * ((D1 - d1) + hF1) - corr1 + c.q1 * gg;
+  dm[2] = T(2) * hF2 - c.s_eps * d2 - c.q2 * gg;
+  dm[4] = T(2) * hF4 - c.s_q * d4;
+  dm[6] = T(2) * hF6 - c.s_q * d6;
+  dm[7] = T(2) * ((D7 - d7) + hF7) - corr7 + c.q7 * (gx * gx - gy * gy);
+  dm[8] = T(2) * ((D8 - d8) + hF8) - corr8 + c.q7 * (gx * gy);
 }
 
-// f-bar from pre-collision f at one node, given its exact mass
-// (density_exact(f)) and the stencil gradient g.
-template <typename T, bool kExactMass = true>
-__host__ __device__ __forceinline__ void collide_node(T* f, double mass, T gx, T gy, const Coef<T>& c) {
-  T m[9];
+// f-bar from pre-collision f at one node of density rho (density(f)), given
+// the stencil gradient g.
+template <typename T>
+__host__ __device__ __forceinline__ void collide_node(T* f, T rho, T gx, T gy, const Coef<T>& c) {
+  T m[9], dm[9];
   forward_moments(f, m);
-  m[0] = (T)mass;
-  const NodeState<T> s = node_state(m[0], m[3], m[5], gx, gy, c);
-  collide_moments(m, s, gx, gy, c);
-  inverse_moments<T, kExactMass>(m, f, mass);
+  const NodeState<T> s = node_state(rho, m[3], m[5], gx, gy, c);
+  collide_delta(m, s, gx, gy, c, dm);
+  add_inverse_moments(dm, s.Fx, s.Fy, f);
 }
 
 // Equilibrium populations f^eq = M^-1 m^eq(rho, u, eta(rho)).
@@ -250,7 +253,7 @@ __host__ __device__ __forceinline__ void equilibrium_node(T rho, T ux, T uy, con
   m[6] = rho * uy * (T(3) * ux2 - T(1));
   m[7] = rho * (ux2 - uy2);
   m[8] = rho * ux * uy;
-  inverse_moments(m, f, (double)rho);
+  inverse_moments(m, f);
 }
 
 // Reference populations of the 2-byte storages: the rest equilibrium
@@ -294,8 +297,8 @@ __host__ __device__ __forceinline__ void transpose_moments(const T* a, T* f) {
 // populations f, the stencil gradient g and lam = dL/d f-bar, returns
 // lam_f = dL/d f (at fixed g), a_g = dL/d g, and adds dL/d(G'^2, K', R T)
 // to a_th.  The forward quantities are recomputed here; the sweep visits the
-// assignments of collide_node / collide_moments / node_state / eos in
-// reverse order.
+// assignments of collide_node / collide_delta / node_state / eos in
+// reverse order (differentiating m-bar = m + dm).
 template <typename T>
 __host__ __device__ __forceinline__ void collide_node_vjp(const T* f, T gx, T gy, const Coef<T>& c, const T* lam,
                                                           T* lam_f, T& a_gx, T& a_gy, T* a_th) {
@@ -351,7 +354,7 @@ __host__ __device__ __forceinline__ void collide_node_vjp(const T* f, T gx, T gy
   T a_rho = l[0], a_ux = 0, a_uy = 0, a_Fx = l[3], a_Fy = l[5], a_dp = 0, a_eta = 0, a_g2 = 0;
   T a_m[9] = {0, 0, 0, l[3], 0, l[5], 0, 0, 0};
   a_gx = 0, a_gy = 0;
-  // post-collision rows (see collide_moments step (5)-(6))
+  // post-collision rows (see collide_delta steps (5)-(6))
   T a_meq1 = l[1], a_hF1 = l[1], a_d1 = -l[1], a_D1 = T(2) * l[1], a_c1 = -l[1];
   T a_gg = c.q1 * l[1] - c.s_eps * T(0.5) * c.g2 * l[2];
   a_g2 += T(0.5) * (c.s_e - c.kq2) * gg * l[1] - c.s_eps * T(0.5) * gg * l[2];

@@ -61,11 +61,8 @@ constexpr int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 __device__ __forceinline__ uint16_t f32_to_f16(float v) { return __half_as_ushort(__float2half_rn(v)); }
 __device__ __forceinline__ float f16_to_f32(uint16_t h) { return __half2float(__ushort_as_half(h)); }
 
-// binary32 -> bfloat16, round to nearest even (finite inputs).
-__device__ __forceinline__ uint16_t f32_to_bf16(float v) {
-  const uint32_t b = __float_as_uint(v);
-  return (uint16_t)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
-}
+// binary32 -> bfloat16, round to nearest even (one v_cvt_pk_bf16_f32).
+__device__ __forceinline__ uint16_t f32_to_bf16(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // The reference density rho~ of a node: its density rounded to binary16.
@@ -271,39 +268,40 @@ __device__ __forceinline__ void issue_tile(const Planes<typename St::E>& P, cons
 }
 
 // The three class values of the reference equilibrium at the reference
-// density of a tile node (2-byte storages), staged for the encoders of the
-// node's neighbours: sref[class * LDS + pos].
+// density of a tile node (2-byte storages), times -S, staged for the
+// encoders of the node's neighbours: sref[class * LDS + pos] (the encoder
+// is then one fused multiply-add, S f + (-S f_ref)).
 template <class S>
 __device__ __forceinline__ void stage_ref(const RefPoly<float>& q, float rho, int pos, float* sref) {
   const float rt = ref_density(rho);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) sref[c * S::LDS + pos] = ref_value(q, c, rt);
+  for (int c = 0; c < 3; ++c) sref[c * S::LDS + pos] = -q.scale * ref_value(q, c, rt);
 }
 
 // Decode the tile, stage densities of the tile and its ring into
-// srho[(TY+2)][LW], keep the own nodes' populations and masses (exact FP64
-// sum for F32) in registers.
+// srho[(TY+2)][LW], keep the own nodes' populations and densities in
+// registers.
 template <class S, class St>
 __device__ __forceinline__ void stage_tile(const TileRegs<S, St>& R, const RefPoly<float>& q,
-                                           float (&f)[S::NPT][9], double (&mass)[S::NPT], float* srho,
+                                           float (&f)[S::NPT][9], float (&rho)[S::NPT], float* srho,
                                            float* sref) {
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * S::TX + tx;
 #pragma unroll
   for (int k = 0; k < S::NPT; ++k) {
     decode<St>(R.raw[k], St::kRef ? R.rref[k] : 0, q, f[k]);
-    mass[k] = St::kRef ? (double)density(f[k]) : density_exact(f[k]);
+    rho[k] = density(f[k]);
     const int pos = (ty + k * S::WY + 1) * S::LW + tx + 1;
-    srho[pos] = (float)mass[k];
-    if (St::kRef && sref) stage_ref<S>(q, (float)mass[k], pos, sref);
+    srho[pos] = rho[k];
+    if (St::kRef && sref) stage_ref<S>(q, rho[k], pos, sref);
   }
   if (tid < S::NRING) {
     int hx, hy;
     ring_slot<S>(tid, hx, hy);
     float fr[9];
     decode<St>(R.rraw, St::kRef ? R.rrref : 0, q, fr);
-    const float rho = St::kRef ? density(fr) : (float)density_exact(fr);
-    srho[hy * S::LW + hx] = rho;
-    if (St::kRef && sref) stage_ref<S>(q, rho, hy * S::LW + hx, sref);
+    const float r = density(fr);
+    srho[hy * S::LW + hx] = r;
+    if (St::kRef && sref) stage_ref<S>(q, r, hy * S::LW + hx, sref);
   }
 }
 
@@ -331,11 +329,11 @@ __global__ __launch_bounds__(S::NTHREADS) void step_kernel(const void* __restric
   const int tile = xcd_tile(blockIdx.x, ntiles);
   const int x0 = (tile % ntx) * S::TX, y0 = (tile / ntx) * S::TY;
   float f[S::NPT][9];
-  double mass[S::NPT];
+  float rho[S::NPT];
   {
     TileRegs<S, St> R;
     issue_tile<S, St>(planes<E>(src, N), ref_in, nx, ny, x0, y0, R);
-    stage_tile<S, St>(R, q, f, mass, srho, St::kRef ? sref : nullptr);
+    stage_tile<S, St>(R, q, f, rho, srho, St::kRef ? sref : nullptr);
   }
   __syncthreads();
   const int x = x0 + threadIdx.x;
@@ -350,15 +348,14 @@ __global__ __launch_bounds__(S::NTHREADS) void step_kernel(const void* __restric
     neighbours<S>(srho, threadIdx.x + 1, ly + 1, nb);
     float gx, gy;
     stencil(nb[1], nb[2], nb[3], nb[4], nb[5], nb[6], nb[7], nb[8], gx, gy);
-    collide_node<float, !St::kRef>(f[k], mass[k], gx, gy, c);
+    collide_node<float>(f[k], rho[k], gx, gy, c);
     E out[9];
     if constexpr (St::kRef) {
       // f-bar_i streams to x + e_i: encode it against that node's reference
       const int pos = (ly + 1) * S::LW + threadIdx.x + 1;
 #pragma unroll
       for (int i = 0; i < 9; ++i)
-        out[i] = St::from_f32((f[k][i] - sref[velocity_class(i) * S::LDS + pos + kCy[i] * S::LW + kCx[i]]) *
-                              q.scale);
+        out[i] = St::from_f32(fmaf(f[k][i], q.scale, sref[velocity_class(i) * S::LDS + pos + kCy[i] * S::LW + kCx[i]]));
       ref_out[(size_t)y * nx + x] = f32_to_f16(nb[0]);
     } else {
 #pragma unroll
@@ -383,11 +380,11 @@ __global__ __launch_bounds__(MomTile::NTHREADS) void moments_kernel(
   const size_t N = (size_t)nx * ny;
   const int x0 = (blockIdx.x % ntx) * S::TX, y0 = (blockIdx.x / ntx) * S::TY;
   float f[S::NPT][9];
-  double mass[S::NPT];
+  float rho[S::NPT];
   {
     TileRegs<S, St> R;
     issue_tile<S, St>(planes<typename St::E>(src, N), ref_in, nx, ny, x0, y0, R);
-    stage_tile<S, St>(R, q, f, mass, srho, nullptr);
+    stage_tile<S, St>(R, q, f, rho, srho, nullptr);
   }
   __syncthreads();
   const int x = x0 + threadIdx.x;
@@ -398,7 +395,6 @@ __global__ __launch_bounds__(MomTile::NTHREADS) void moments_kernel(
     if (x >= nx || y >= ny) continue;
     float m[9];
     forward_moments(f[k], m);
-    m[0] = (float)mass[k];
     float nb[9], gx, gy;
     neighbours<S>(srho, threadIdx.x + 1, ly + 1, nb);
     stencil(nb[1], nb[2], nb[3], nb[4], nb[5], nb[6], nb[7], nb[8], gx, gy);
@@ -407,7 +403,7 @@ __global__ __launch_bounds__(MomTile::NTHREADS) void moments_kernel(
     if (rho_out) rho_out[o] = m[0];
     if (ux_out) ux_out[o] = s.ux;
     if (uy_out) uy_out[o] = s.uy;
-    sm += mass[k];
+    sm += (double)m[0];
     sx += (double)m[3];
     sy += (double)m[5];
   }
@@ -608,11 +604,11 @@ __global__ __launch_bounds__(S::NTHREADS) void adjoint_step_kernel(const float* 
   const int tile = xcd_tile(blockIdx.x, ntiles);
   const int x0 = (tile % ntx) * S::TX, y0 = (tile / ntx) * S::TY;
   float f[S::NPT][9];
-  double mass[S::NPT];
+  float rho[S::NPT];
   {
     TileRegs<S, StoreF32> R;
     issue_tile<S, StoreF32>(planes<float>(fsrc, N), nullptr, nx, ny, x0, y0, R);
-    stage_tile<S, StoreF32>(R, RefPoly<float>{}, f, mass, srho, nullptr);
+    stage_tile<S, StoreF32>(R, RefPoly<float>{}, f, rho, srho, nullptr);
   }
   stage_nu<S>(adj_in + 9 * N, adj_in + 10 * N, nx, ny, x0, y0, sa, snu);  // barrier covers srho too
   const Planes<float> P = planes<float>(adj_in, N);
@@ -750,6 +746,8 @@ Coef<float> make_coef(const lbm_derived& d, double varpi, double a, double b) {
   c.s_p = sp;
   c.q1 = (se - c.kq2) * 0.5 * d.g2;
   c.q7 = sp * d.g2 / 12.0;
+  c.q2 = seps * 0.5 * d.g2;
+  c.s_q = sq;
   Coef<float> f;
   const double* src = reinterpret_cast<const double*>(&c);
   float* dstp = reinterpret_cast<float*>(&f);

@@ -20,6 +20,11 @@ STORAGES = ["fp16", "bf16"]
 # one rounding of a deviation of ~1e-3 rho per step is ~2^-12 (FP16) or
 # ~2^-9 (BF16) of it; the bounds leave a factor ~5 over what the run shows.
 STEP_TOL = {"fp16": 1e-4, "bf16": 1e-3}
+# Coexistence densities of the 2-byte runs against the FP32 run, / rho_l.  A
+# relaxed interface repeats the same roundings every step, so the storage
+# leaves a steady offset rather than noise; FP16 (11 significand bits, S =
+# 2^12) stays within 1e-4, and BF16 keeps 3 bits fewer: 2^3 times that.
+COEX_VS_FP32 = {"fp16": 1e-4, "bf16": 8e-4}
 
 
 def droplet(n=96, tr=0.7):
@@ -70,7 +75,7 @@ def test_ragged_lattice_runs_and_matches_fp32(storage):
 def test_coexistence_error(storage):
     """Flat interface relaxed for 20000 steps at T_r = 0.7: coexistence
     densities within 1e-3 of rho_l of the Maxwell values, and the 2-byte
-    result within 1e-4 of rho_l of the FP32 one."""
+    result within COEX_VS_FP32 of rho_l of the FP32 one."""
     _, co = params_pair(4, 128, tr=0.7, width=10.0)
     rho = wl.flat_slab(4, 128, co.rho_g, co.rho_l, co.width / wl.TANH_WIDTH_FACTOR)
 
@@ -84,7 +89,8 @@ def test_coexistence_error(storage):
     assert abs(g - co.rho_g) / co.rho_l <= 1e-3
     if storage != "fp32":
         g32, l32 = run("fp32")
-        assert abs(l - l32) / co.rho_l <= 1e-4 and abs(g - g32) / co.rho_l <= 1e-4
+        tol = COEX_VS_FP32[storage]
+        assert abs(l - l32) / co.rho_l <= tol and abs(g - g32) / co.rho_l <= tol, (l - l32, g - g32)
 
 
 @pytest.mark.parametrize("storage", STORAGES)
