@@ -246,11 +246,45 @@ struct TileRegs {
   uint16_t rrref;
 };
 
-// Issue the loads of the tile at (x0, y0); ring loads first.
-template <class S, class St>
+// Whether the tile at (x0, y0), its ring and the ring's pull sources lie
+// inside the lattice without wrapping (the common case on large lattices).
+template <class S>
+__device__ __forceinline__ bool interior_tile(int x0, int y0, int nx, int ny) {
+  return x0 >= 2 && y0 >= 2 && x0 + S::TX + 2 <= nx && y0 + S::TY + 2 <= ny;
+}
+
+// Issue the loads of the tile at (x0, y0); ring loads first.  kInterior
+// (interior_tile true): every plane's pull shift goes into its uniform base,
+// so the nine loads of a node share one offset register.
+template <class S, class St, bool kInterior = false>
 __device__ __forceinline__ void issue_tile(const Planes<typename St::E>& P, const uint16_t* __restrict__ rho_ref,
                                            int nx, int ny, int x0, int y0, TileRegs<S, St>& R) {
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * S::TX + tx;
+  if constexpr (kInterior) {
+    using E = typename St::E;
+    const unsigned rb = St::ES * (unsigned)nx;
+    Planes<E> Q;  // Q_i + offset(x) = P_i + offset(x - e_i)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Q.p[i] = P.p[i] - (ptrdiff_t)kCy[i] * rb - kCx[i] * St::ES;
+    const char* rref = reinterpret_cast<const char*>(rho_ref);  // 2-byte plane: same offsets as ES = 2
+    if (tid < S::NRING) {
+      int hx, hy;
+      ring_slot<S>(tid, hx, hy);
+      const unsigned off = (unsigned)(y0 + hy - 1) * rb + (unsigned)(x0 + hx - 1) * St::ES;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) R.rraw[i] = ldb<E>(Q.p[i], off);
+      if constexpr (St::kRef) R.rrref = ldb<uint16_t>(rref, off);
+    }
+    const unsigned off0 = (unsigned)(y0 + ty) * rb + (unsigned)(x0 + tx) * St::ES;
+#pragma unroll
+    for (int k = 0; k < S::NPT; ++k) {
+      const unsigned off = off0 + (unsigned)(k * S::WY) * rb;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) R.raw[k][i] = ldb<E>(Q.p[i], off);
+      if constexpr (St::kRef) R.rref[k] = ldb<uint16_t>(rref, off);
+    }
+    return;
+  }
   if (tid < S::NRING) {
     int hx, hy;
     ring_slot<S>(tid, hx, hy);
@@ -332,7 +366,10 @@ __global__ __launch_bounds__(S::NTHREADS) void step_kernel(const void* __restric
   float rho[S::NPT];
   {
     TileRegs<S, St> R;
-    issue_tile<S, St>(planes<E>(src, N), ref_in, nx, ny, x0, y0, R);
+    if (interior_tile<S>(x0, y0, nx, ny))
+      issue_tile<S, St, true>(planes<E>(src, N), ref_in, nx, ny, x0, y0, R);
+    else
+      issue_tile<S, St, false>(planes<E>(src, N), ref_in, nx, ny, x0, y0, R);
     stage_tile<S, St>(R, q, f, rho, srho, St::kRef ? sref : nullptr);
   }
   __syncthreads();
@@ -340,6 +377,7 @@ __global__ __launch_bounds__(S::NTHREADS) void step_kernel(const void* __restric
   if (x >= nx) return;
   const OutPlanes<E> Q = out_planes<E>(dst, N);
   const unsigned rb = St::ES * (unsigned)nx;
+  const unsigned o0 = rb * (unsigned)(y0 + threadIdx.y) + St::ES * (unsigned)x;
 #pragma unroll
   for (int k = 0; k < S::NPT; ++k) {
     const int ly = threadIdx.y + k * S::WY, y = y0 + ly;
@@ -356,12 +394,12 @@ __global__ __launch_bounds__(S::NTHREADS) void step_kernel(const void* __restric
 #pragma unroll
       for (int i = 0; i < 9; ++i)
         out[i] = St::from_f32(fmaf(f[k][i], q.scale, sref[velocity_class(i) * S::LDS + pos + kCy[i] * S::LW + kCx[i]]));
-      ref_out[(size_t)y * nx + x] = f32_to_f16(nb[0]);
     } else {
 #pragma unroll
       for (int i = 0; i < 9; ++i) out[i] = f[k][i];
     }
-    const unsigned o = rb * (unsigned)y + St::ES * (unsigned)x;
+    const unsigned o = o0 + (unsigned)(k * S::WY) * rb;
+    if constexpr (St::kRef) *reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(ref_out) + o) = f32_to_f16(nb[0]);
 #pragma unroll
     for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(out[i], reinterpret_cast<E*>(Q.p[i] + o));
   }
@@ -543,14 +581,15 @@ struct AdjLds {
 
 // A on the tile plus a two-node ring into sa[2][AH][AW], then nu on the tile
 // plus a one-node ring into snu[(TY+2)][LW].  Ends with a barrier.
-template <class S>
+template <class S, bool kInterior = false>
 __device__ __forceinline__ void stage_nu(const float* __restrict__ ax, const float* __restrict__ ay, int nx, int ny,
                                          int x0, int y0, float* sa, float* snu) {
   using L = AdjLds<S>;
   const int tid = threadIdx.y * S::TX + threadIdx.x;
   for (int p = tid; p < L::NA; p += S::NTHREADS) {
     const int hx = p % L::AW, hy = p / L::AW;
-    const size_t o = (size_t)wrap(y0 + hy - 2, ny) * nx + wrap(x0 + hx - 2, nx);
+    const size_t o = kInterior ? (size_t)(y0 + hy - 2) * nx + (x0 + hx - 2)
+                               : (size_t)wrap(y0 + hy - 2, ny) * nx + wrap(x0 + hx - 2, nx);
     sa[p] = ax[o];
     sa[L::NA + p] = ay[o];
   }
@@ -590,30 +629,27 @@ __device__ __forceinline__ void block_accumulate(const float* th, double* red, d
   if (tid < 3) partials[(size_t)blockIdx.x * 3 + tid] += red[tid * S::NTHREADS];
 }
 
-template <class S>
-__global__ __launch_bounds__(S::NTHREADS) void adjoint_step_kernel(const float* __restrict__ fsrc,
-                                                                   const float* __restrict__ adj_in,
-                                                                   float* __restrict__ adj_out,
-                                                                   double* __restrict__ partials, int nx, int ny,
-                                                                   int ntx, int ntiles, Coef<float> c) {
-  using L = AdjLds<S>;
-  __shared__ float srho[S::LDS];
-  __shared__ float snu[S::LDS];
-  __shared__ __align__(8) float sa[2 * L::NA];
+// One tile of the adjoint step (kInterior: interior_tile holds, no wrap).
+template <class S, bool kInterior>
+__device__ __forceinline__ void adjoint_tile(const float* __restrict__ fsrc, const float* __restrict__ adj_in,
+                                             float* __restrict__ adj_out, int nx, int ny, int x0, int y0,
+                                             const Coef<float>& c, float* srho, float* snu, float* sa, float* th) {
   const size_t N = (size_t)nx * ny;
-  const int tile = xcd_tile(blockIdx.x, ntiles);
-  const int x0 = (tile % ntx) * S::TX, y0 = (tile / ntx) * S::TY;
   float f[S::NPT][9];
   float rho[S::NPT];
   {
     TileRegs<S, StoreF32> R;
-    issue_tile<S, StoreF32>(planes<float>(fsrc, N), nullptr, nx, ny, x0, y0, R);
+    issue_tile<S, StoreF32, kInterior>(planes<float>(fsrc, N), nullptr, nx, ny, x0, y0, R);
     stage_tile<S, StoreF32>(R, RefPoly<float>{}, f, rho, srho, nullptr);
   }
-  stage_nu<S>(adj_in + 9 * N, adj_in + 10 * N, nx, ny, x0, y0, sa, snu);  // barrier covers srho too
+  stage_nu<S, kInterior>(adj_in + 9 * N, adj_in + 10 * N, nx, ny, x0, y0, sa, snu);  // barrier covers srho too
   const Planes<float> P = planes<float>(adj_in, N);
-  float th[3] = {0.0f, 0.0f, 0.0f};
+  const unsigned rb = 4u * (unsigned)nx;
+  Planes<float> Q;  // interior: Q_i + offset(y) = P_i + offset(y + e_i)
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Q.p[i] = P.p[i] + (ptrdiff_t)kCy[i] * rb + kCx[i] * 4;
   const int x = x0 + threadIdx.x;
+  const unsigned o0 = rb * (unsigned)(y0 + threadIdx.y) + 4u * (unsigned)x;
 #pragma unroll
   for (int k = 0; k < S::NPT; ++k) {
     const int ly = threadIdx.y + k * S::WY, y = y0 + ly;
@@ -624,27 +660,53 @@ __global__ __launch_bounds__(S::NTHREADS) void adjoint_step_kernel(const float* 
     float gx, gy;
     stencil(nb[1], nb[2], nb[3], nb[4], nb[5], nb[6], nb[7], nb[8], gx, gy);
     // lam-bar_i(y) = L_i(y + e_i) + nu(y + e_i)
-    const NodeAddr<4> a = node_addr<4>(x, y, nx, ny);
+    const unsigned o = o0 + (unsigned)(k * S::WY) * rb;
     float lb[9];
-    lb[0] = ldb<float>(P.p[0], a.r0 + a.c0);
-    lb[1] = ldb<float>(P.p[1], a.r0 + a.cp);
-    lb[2] = ldb<float>(P.p[2], a.rp + a.c0);
-    lb[3] = ldb<float>(P.p[3], a.r0 + a.cm);
-    lb[4] = ldb<float>(P.p[4], a.rm + a.c0);
-    lb[5] = ldb<float>(P.p[5], a.rp + a.cp);
-    lb[6] = ldb<float>(P.p[6], a.rp + a.cm);
-    lb[7] = ldb<float>(P.p[7], a.rm + a.cm);
-    lb[8] = ldb<float>(P.p[8], a.rm + a.cp);
+    if constexpr (kInterior) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) lb[i] = ldb<float>(Q.p[i], o);
+    } else {
+      const NodeAddr<4> a = node_addr<4>(x, y, nx, ny);
+      lb[0] = ldb<float>(P.p[0], a.r0 + a.c0);
+      lb[1] = ldb<float>(P.p[1], a.r0 + a.cp);
+      lb[2] = ldb<float>(P.p[2], a.rp + a.c0);
+      lb[3] = ldb<float>(P.p[3], a.r0 + a.cm);
+      lb[4] = ldb<float>(P.p[4], a.rm + a.c0);
+      lb[5] = ldb<float>(P.p[5], a.rp + a.cp);
+      lb[6] = ldb<float>(P.p[6], a.rp + a.cm);
+      lb[7] = ldb<float>(P.p[7], a.rm + a.cm);
+      lb[8] = ldb<float>(P.p[8], a.rm + a.cp);
+    }
 #pragma unroll
     for (int i = 0; i < 9; ++i) lb[i] += snu[pos + kCy[i] * S::LW + kCx[i]];
     float lf[9], agx = 0.0f, agy = 0.0f;
     collide_node_vjp<float>(f[k], gx, gy, c, lb, lf, agx, agy, th);
-    const size_t o = (size_t)y * nx + x;
+    char* out = reinterpret_cast<char*>(adj_out);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(lf[i], adj_out + (size_t)i * N + o);
-    __builtin_nontemporal_store(agx, adj_out + 9 * N + o);
-    __builtin_nontemporal_store(agy, adj_out + 10 * N + o);
+    for (int i = 0; i < 9; ++i)
+      __builtin_nontemporal_store(lf[i], reinterpret_cast<float*>(out + (size_t)i * N * 4 + o));
+    __builtin_nontemporal_store(agx, reinterpret_cast<float*>(out + 9 * N * 4 + o));
+    __builtin_nontemporal_store(agy, reinterpret_cast<float*>(out + 10 * N * 4 + o));
   }
+}
+
+template <class S>
+__global__ __launch_bounds__(S::NTHREADS) void adjoint_step_kernel(const float* __restrict__ fsrc,
+                                                                   const float* __restrict__ adj_in,
+                                                                   float* __restrict__ adj_out,
+                                                                   double* __restrict__ partials, int nx, int ny,
+                                                                   int ntx, int ntiles, Coef<float> c) {
+  using L = AdjLds<S>;
+  __shared__ float srho[S::LDS];
+  __shared__ float snu[S::LDS];
+  __shared__ __align__(8) float sa[2 * L::NA];
+  const int tile = xcd_tile(blockIdx.x, ntiles);
+  const int x0 = (tile % ntx) * S::TX, y0 = (tile / ntx) * S::TY;
+  float th[3] = {0.0f, 0.0f, 0.0f};
+  if (interior_tile<S>(x0, y0, nx, ny))
+    adjoint_tile<S, true>(fsrc, adj_in, adj_out, nx, ny, x0, y0, c, srho, snu, sa, th);
+  else
+    adjoint_tile<S, false>(fsrc, adj_in, adj_out, nx, ny, x0, y0, c, srho, snu, sa, th);
   block_accumulate<S>(th, reinterpret_cast<double*>(sa), partials);
 }
 
