@@ -17,7 +17,8 @@
  *  - Field and buffer pointers (f, f_*, rho*, u*, lam, adj*, drho0, src,
  *    dst) are DEVICE pointers owned by the caller (any allocator; the
  *    library never frees them).  The result pointers out, sigma_out,
- *    totals, dtheta and jac are HOST pointers.
+ *    totals, dtheta, jac and which, and the pointer arrays bufs and
+ *    f_states (whose elements are device pointers), are HOST pointers.
  *  - Every call is asynchronous on the stream given to lbm_create (or
  *    lbm_set_stream), except where stated: lbm_init, lbm_moments (with
  *    totals) and lbm_adjoint_theta (with dtheta) synchronise that stream to
@@ -180,6 +181,12 @@ int lbm_load_state(lbm_ctx* ctx, const void* src, int64_t t);
  * recomputation of a checkpoint segment for the adjoint.  LBM_FP32 only. */
 int lbm_step_saved(lbm_ctx* ctx, const void* src, void* dst);
 
+/* n steps from checkpoint to checkpoint: bufs[j+1] := step(bufs[j]) for
+ * j = 0 .. n-1 (a host array of n+1 device checkpoint buffers, consecutive
+ * ones distinct), each as lbm_step_saved.  One call recomputes a checkpoint
+ * segment.  LBM_FP32 only. */
+int lbm_step_saved_chain(lbm_ctx* ctx, void* const* bufs, int32_t n);
+
 /* ---- Adjoint (reverse mode) of a rollout; LBM_FP32 storage only ---------
  * For a scalar loss L of the state, the adjoint of time t is
  * Lambda_i(x, t) = dL/d f_i(x, t) of the post-streaming populations.  One
@@ -210,6 +217,15 @@ int lbm_adjoint_seed(lbm_ctx* ctx, const float* lam, void* adj);
  * t+1, adj_out (a different buffer) receives that of time t.  Adds the
  * theta terms of this step to the accumulator. */
 int lbm_adjoint_step(lbm_ctx* ctx, const void* f_t, const void* adj_next, void* adj_out);
+
+/* n adjoint steps back through a segment: f_states[j] (host array of n
+ * device checkpoints) is the forward state of time t0 + j; the adjoint state
+ * of time t0 + n is in adj_a on entry.  The steps run from j = n-1 down to 0,
+ * alternating between adj_a and adj_b; on return *which (host) is 0 if the
+ * adjoint of time t0 is in adj_a, 1 if in adj_b.  Adds the theta terms of
+ * every step to the accumulator. */
+int lbm_adjoint_run(lbm_ctx* ctx, const void* const* f_states, int32_t n, void* adj_a, void* adj_b,
+                    int32_t* which);
 
 /* lam := Lambda of the adjoint state adj (device float, 9*nx*ny). */
 int lbm_adjoint_get(lbm_ctx* ctx, const void* adj, float* lam);

@@ -1,6 +1,7 @@
 """Build the HIP library ``liblbm.so`` for gfx950 with hipcc, in place.
 
-Usage: ``python -m paper_1809_02390_amd.build`` (or ``build()`` from Python).
+Usage: ``python paper_1809_02390_amd/build.py`` (by path: importing the
+package would load the library being rebuilt), or ``__graft_entry__.build()``.
 """
 from __future__ import annotations
 

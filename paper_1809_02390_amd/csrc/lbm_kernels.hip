@@ -570,13 +570,17 @@ __global__ __launch_bounds__(BLK) void get_state_kernel(const void* __restrict__
 //   (L_i(y), A(y), dtheta) = transposed Jacobian of the collision at y
 //                            (rho and g recomputed as the forward step has them)
 // ---------------------------------------------------------------------------
-using AdjTile = TileShape<128, 8, 4>;
+#ifndef LBM_ADJ_TILE
+#define LBM_ADJ_TILE 128, 4, 4
+#endif
+using AdjTile = TileShape<LBM_ADJ_TILE>;
 
 template <class S>
 struct AdjLds {
   static constexpr int AW = S::TX + 4, AH = S::TY + 4, NA = AW * AH;
   static constexpr int NRED = 3 * S::NTHREADS;  // doubles of the block reduction
-  static_assert(NRED * 2 <= 2 * NA, "reduction reuses the A halo");
+  // floats of the LDS buffer that holds the A halo, then the reduction
+  static constexpr int NSA = 2 * NA > 2 * NRED ? 2 * NA : 2 * NRED;
 };
 
 // A on the tile plus a two-node ring into sa[2][AH][AW], then nu on the tile
@@ -699,7 +703,7 @@ __global__ __launch_bounds__(S::NTHREADS) void adjoint_step_kernel(const float* 
   using L = AdjLds<S>;
   __shared__ float srho[S::LDS];
   __shared__ float snu[S::LDS];
-  __shared__ __align__(8) float sa[2 * L::NA];
+  __shared__ __align__(8) float sa[L::NSA];
   const int tile = xcd_tile(blockIdx.x, ntiles);
   const int x0 = (tile % ntx) * S::TX, y0 = (tile / ntx) * S::TY;
   float th[3] = {0.0f, 0.0f, 0.0f};
@@ -720,7 +724,7 @@ __global__ __launch_bounds__(S::NTHREADS) void adjoint_finish_kernel(
     int ntx, Coef<float> c) {
   using L = AdjLds<S>;
   __shared__ float snu[S::LDS];
-  __shared__ __align__(8) float sa[2 * L::NA];
+  __shared__ __align__(8) float sa[L::NSA];
   const size_t N = (size_t)nx * ny;
   const int x0 = (blockIdx.x % ntx) * S::TX, y0 = (blockIdx.x / ntx) * S::TY;
   stage_nu<S>(adj + 9 * N, adj + 10 * N, nx, ny, x0, y0, sa, snu);
@@ -1168,6 +1172,25 @@ int lbm_step_saved(lbm_ctx* ctx, const void* src, void* dst) {
   return LBM_OK;
 }
 
+int lbm_step_saved_chain(lbm_ctx* ctx, void* const* bufs, int32_t n) {
+  if (int st = check_ctx(ctx, false)) return st;
+  if (int st = need_fp32(ctx, "lbm_step_saved_chain")) return st;
+  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+  if (n == 0) return LBM_OK;
+  if (!bufs) return fail(LBM_EINVAL, "bufs is NULL");
+  for (int32_t j = 0; j < n; ++j)
+    if (!bufs[j] || !bufs[j + 1] || bufs[j] == bufs[j + 1])
+      return fail(LBM_EINVAL, "bufs[%d] and bufs[%d] must be two distinct device buffers", j, j + 1);
+  if (int st = set_device(ctx)) return st;
+  using S = StepTile;
+  const int ntx = tiles_x<S>(ctx->p.nx), ntiles = tiles_total<S>(ctx->p.nx, ctx->p.ny);
+  for (int32_t j = 0; j < n; ++j)
+    step_kernel<S, StoreF32><<<ntiles, dim3(S::TX, S::WY), 0, ctx->stream>>>(
+        bufs[j], bufs[j + 1], nullptr, nullptr, ctx->p.nx, ctx->p.ny, ntx, ntiles, ctx->c, ctx->q);
+  HIP_OK(hipGetLastError());
+  return LBM_OK;
+}
+
 size_t lbm_adjoint_bytes(const lbm_params* p) {
   char msg[256];
   if (lbm::validate(p, msg, sizeof msg) || p->storage != LBM_FP32) return 0;
@@ -1197,6 +1220,32 @@ int lbm_adjoint_step(lbm_ctx* ctx, const void* f_t, const void* adj_next, void* 
       static_cast<const float*>(f_t), static_cast<const float*>(adj_next), static_cast<float*>(adj_out),
       ctx->theta, ctx->p.nx, ctx->p.ny, ntx, ntiles, ctx->c);
   HIP_OK(hipGetLastError());
+  return LBM_OK;
+}
+
+int lbm_adjoint_run(lbm_ctx* ctx, const void* const* f_states, int32_t n, void* adj_a, void* adj_b,
+                    int32_t* which) {
+  if (int st = check_ctx(ctx, false)) return st;
+  if (int st = need_fp32(ctx, "the adjoint")) return st;
+  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+  if (!which) return fail(LBM_EINVAL, "which is NULL");
+  if (!adj_a || !adj_b || adj_a == adj_b) return fail(LBM_EINVAL, "adj_a and adj_b must be two distinct device buffers");
+  if (n > 0 && !f_states) return fail(LBM_EINVAL, "f_states is NULL");
+  for (int32_t j = 0; j < n; ++j)
+    if (!f_states[j]) return fail(LBM_EINVAL, "f_states[%d] is NULL", j);
+  if (int st = set_device(ctx)) return st;
+  using S = AdjTile;
+  const int ntx = tiles_x<S>(ctx->p.nx), ntiles = ctx->adj_blocks;
+  void* buf[2] = {adj_a, adj_b};
+  int cur = 0;
+  for (int32_t j = n - 1; j >= 0; --j) {
+    adjoint_step_kernel<S><<<ntiles, dim3(S::TX, S::WY), 0, ctx->stream>>>(
+        static_cast<const float*>(f_states[j]), static_cast<const float*>(buf[cur]),
+        static_cast<float*>(buf[cur ^ 1]), ctx->theta, ctx->p.nx, ctx->p.ny, ntx, ntiles, ctx->c);
+    cur ^= 1;
+  }
+  HIP_OK(hipGetLastError());
+  *which = cur;
   return LBM_OK;
 }
 

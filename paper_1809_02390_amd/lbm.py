@@ -46,7 +46,7 @@ class lbm_derived(ctypes.Structure):
 def _load():
     if not os.path.exists(_LIB_PATH):
         raise ImportError(f"HIP library {_LIB_PATH} is missing: build it with "
-                          "`python -m paper_1809_02390_amd.build` (there is no CPU fallback)")
+                          "`python paper_1809_02390_amd/build.py` (there is no CPU fallback)")
     lib = ctypes.CDLL(_LIB_PATH)
     P, V, I, D = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     sig = {
@@ -66,6 +66,8 @@ def _load():
         "lbm_save_state": (I, [V, V]),
         "lbm_load_state": (I, [V, V, ctypes.c_int64]),
         "lbm_step_saved": (I, [V, V, V]),
+        "lbm_step_saved_chain": (I, [V, P(V), ctypes.c_int32]),
+        "lbm_adjoint_run": (I, [V, P(V), ctypes.c_int32, V, V, P(ctypes.c_int32)]),
         "lbm_adjoint_bytes": (ctypes.c_size_t, [P(lbm_params)]),
         "lbm_adjoint_seed": (I, [V, V, V]),
         "lbm_adjoint_step": (I, [V, V, V, V]),
@@ -87,7 +89,7 @@ def _load():
 _lib = _load()
 EXPORTED = ("lbm_last_error", "lbm_derive", "lbm_sigma_paper", "lbm_state_bytes", "lbm_ref_bytes",
             "lbm_create", "lbm_set_stream", "lbm_init", "lbm_set_state", "lbm_get_state", "lbm_step",
-            "lbm_moments", "lbm_checkpoint_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_saved",
+            "lbm_moments", "lbm_checkpoint_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_saved", "lbm_step_saved_chain", "lbm_adjoint_run",
             "lbm_adjoint_bytes", "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_get", "lbm_adjoint_init",
             "lbm_adjoint_theta", "lbm_param_jacobian", "lbm_time", "lbm_get_derived", "lbm_destroy")
 
@@ -213,6 +215,30 @@ def lbm_load_state(ctx, src, t, nbytes):
 
 def lbm_step_saved(ctx, src, dst, nbytes):
     _check(_lib.lbm_step_saved(ctx, _bytes_ptr(src, nbytes, "src"), _bytes_ptr(dst, nbytes, "dst")))
+
+
+def _ptr_array(ts, nbytes, name):
+    arr = (ctypes.c_void_p * len(ts))()
+    for j, t in enumerate(ts):
+        arr[j] = _bytes_ptr(t, nbytes, f"{name}[{j}]")
+    return arr
+
+
+def lbm_step_saved_chain(ctx, bufs, nbytes):
+    """bufs[j+1] := step(bufs[j]) for j < len(bufs) - 1."""
+    if len(bufs) < 2:
+        return
+    _check(_lib.lbm_step_saved_chain(ctx, _ptr_array(bufs, nbytes, "bufs"), len(bufs) - 1))
+
+
+def lbm_adjoint_run(ctx, f_states, adj_a, adj_b, n, state_bytes):
+    """Adjoint steps back through f_states; returns 0 or 1: which of adj_a,
+    adj_b holds the result."""
+    which = ctypes.c_int32(-1)
+    arr = _ptr_array(f_states, state_bytes, "f_states")
+    _check(_lib.lbm_adjoint_run(ctx, arr, len(f_states), _bytes_ptr(adj_a, 44 * n, "adj_a"),
+                                _bytes_ptr(adj_b, 44 * n, "adj_b"), ctypes.byref(which)))
+    return which.value
 
 
 def lbm_adjoint_bytes(params: lbm_params) -> int:
@@ -348,6 +374,14 @@ class Lattice:
     def adjoint_step(self, f_t, adj_next, adj_out):
         lbm_adjoint_step(self.ctx, f_t, adj_next, adj_out, self.n, lbm_checkpoint_bytes(self.params))
         return adj_out
+
+    def step_saved_chain(self, bufs):
+        lbm_step_saved_chain(self.ctx, bufs, lbm_checkpoint_bytes(self.params))
+
+    def adjoint_run(self, f_states, adj_a, adj_b):
+        """Adjoint steps back through f_states; returns the buffer holding the result."""
+        w = lbm_adjoint_run(self.ctx, f_states, adj_a, adj_b, self.n, lbm_checkpoint_bytes(self.params))
+        return adj_a if w == 0 else adj_b
 
     def adjoint_get(self, adj):
         lam = torch.empty((9, self.ny, self.nx), dtype=torch.float32, device=self.f_a.device)

@@ -59,13 +59,13 @@ class Rollout:
         return lat.moments()[0]
 
     def _segment_states(self, s):
-        """States of times t0 .. t0 + m - 1 of segment s, recomputed."""
+        """States of times t0 .. t0 + m - 1 of segment s, recomputed from its
+        checkpoint in one native call."""
         m = min(self.every, self.nsteps - self.starts[s])
         while len(self.pool) < m - 1:
             self.pool.append(self.lat.checkpoint_buffer())
         states = [self.ckpt[s]] + self.pool[:m - 1]
-        for j in range(m - 1):
-            self.lat.step_saved(states[j], states[j + 1])
+        self.lat.step_saved_chain(states)
         return states
 
     def backward_state(self, lam_T):
@@ -73,13 +73,12 @@ class Rollout:
         (9, ny, nx); leaves dL/d theta of the steps in the accumulator."""
         lat = self.lat
         lbm_adjoint_theta(lat.ctx, read=False, reset=True)
-        adj = [lat.adjoint_seed(lam_T), lat.adjoint_buffer()]
+        a, b = lat.adjoint_seed(lam_T), lat.adjoint_buffer()
         for s in reversed(range(len(self.starts))):
-            states = self._segment_states(s)
-            for f_t in reversed(states):
-                lat.adjoint_step(f_t, adj[0], adj[1])
-                adj.reverse()
-        return adj[0]
+            out = lat.adjoint_run(self._segment_states(s), a, b)
+            if out is b:
+                a, b = b, a
+        return a
 
     def backward(self, grad_rho_T):
         """(dL/d rho0 (ny, nx) float32, dL/d theta (3,), dL/d(sigma, W, T_r) (3,))

@@ -10,6 +10,9 @@ largest term: bound 1e-5 of max |lambda| (about 80 ulps).  Parameter sums
 are FP64 sums of FP32 node terms: bound 1e-5 of the sum of |terms|, with
 the terms taken from the oracle.  Rollout gradients carry the FP32 forward
 (relative state error ~1e-6) through the loss: bound 1e-4 relative."""
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -133,6 +136,32 @@ def test_step_saved_is_bitwise_lbm_step():
     assert torch.equal(bufs[1], bufs[2])
 
 
+def test_native_segment_calls_match_single_steps():
+    """lbm_step_saved_chain and lbm_adjoint_run give bitwise the results of
+    the one-step calls they loop over."""
+    nx, ny, n = 70, 37, 5
+    _, co = params_pair(nx, ny, tr=0.8)
+    rho = wl.droplets(nx, ny, co.rho_g, co.rho_l, co.width, [(30, 20)], [11.0])
+    lat = pkg.Lattice(nx, ny, tr=0.8).init(rho)
+    chain = [lat.save_state()] + [lat.checkpoint_buffer() for _ in range(n)]
+    lat.step_saved_chain(chain)
+    single = [chain[0]] + [lat.checkpoint_buffer() for _ in range(n)]
+    for j in range(n):
+        lat.step_saved(single[j], single[j + 1])
+    assert all(torch.equal(a, b) for a, b in zip(chain, single))
+    lam = np.random.default_rng(3).standard_normal((9, ny, nx))
+    a, b = lat.adjoint_seed(lam), lat.adjoint_buffer()
+    lat.adjoint_theta(reset=True)
+    out = lat.adjoint_run(chain[:n], a, b)
+    th_run = lat.adjoint_theta(reset=True)
+    x, y = lat.adjoint_seed(lam), lat.adjoint_buffer()
+    for j in reversed(range(n)):
+        lat.adjoint_step(chain[j], x, y)
+        x, y = y, x
+    th_single = lat.adjoint_theta(reset=True)
+    assert out is b and torch.equal(out, x) and th_run == th_single
+
+
 @pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
 def test_load_state_repeats_the_run(storage):
     nx, ny = 70, 37
@@ -226,3 +255,40 @@ def test_autograd_function_matches_driver_and_is_deterministic(rollout_case):
     assert torch.equal(g1, g2) and torch.equal(p1, p2)
     np.testing.assert_allclose(g1.double().cpu().numpy(), drho0, rtol=0, atol=1e-6 * np.abs(drho0).max())
     np.testing.assert_allclose(p1.numpy(), dp, rtol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# Full-size gradient problem against stored exact derivatives
+# ---------------------------------------------------------------------------
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "droplet512_gradients.json")
+
+
+def test_droplet512_gradient_matches_stored_oracle_derivatives():
+    """512^2 droplet (R = 64) relaxing towards the same-area ellipse for 2000
+    steps, checkpoints every 100 (T_r = 0.8, W = 10, sigma_paper):
+    dL/d(rho0, sigma, W, T_r) of the FP32 forward + adjoint along the eight
+    seeded directions and the three parameter axes, each within 1e-4
+    relative of the exact FP64 derivative written by
+    tests/golden/make_droplet512_gradients.py (oracle only)."""
+    with open(GOLDEN) as fh:
+        g = json.load(fh)
+    n, steps, tr, width, sigma = g["n"], g["nsteps"], g["tr"], g["width"], g["sigma"]
+    co = hm.derive(hm.Params(tr=tr, width=width, sigma=sigma))
+    rho0 = wl.droplets(n, n, co.rho_g, co.rho_l, co.width, [(n / 2, n / 2)], [g["radius"]])
+    target = wl.ellipse(n, n, co.rho_g, co.rho_l, co.width, (n / 2, n / 2), *g["semi_axes"])
+    r = pkg.Rollout(n, n, steps, 100, tr=tr, width=width, sigma=sigma)
+    rho_T = r.forward(rho0).double().cpu().numpy()
+    loss = ((rho_T - target) ** 2).sum()
+    drho0, _, dp = r.backward(torch.tensor(2 * (rho_T - target)))
+    r.release()
+    drho0 = drho0.double().cpu().numpy()
+    assert loss == pytest.approx(g["loss"], rel=1e-5)
+    errs = {}
+    for name, e in g["directions"].items():
+        v = float(np.dot(dp, e["param"]))
+        if e["rho0"]:
+            rng = np.random.default_rng(int(name[4:]))
+            v += float((drho0 * rng.standard_normal((n, n)) * (co.rho_l - co.rho_g) / n).sum())
+        errs[name] = abs(v - e["value"]) / abs(e["value"])
+    print("relative errors:", errs)
+    assert max(errs.values()) <= 1e-4, errs
