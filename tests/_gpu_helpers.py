@@ -40,6 +40,8 @@ def crop_periodic(a, cx, cy, half):
     ny, nx = a.shape[-2:]
     ys = np.arange(cy - half, cy + half + 1) % ny
     xs = np.arange(cx - half, cx + half + 1) % nx
+    if isinstance(a, torch.Tensor):
+        ys, xs = (torch.as_tensor(v, device=a.device) for v in (ys, xs))
     return a[..., ys[:, None], xs[None, :]]
 
 

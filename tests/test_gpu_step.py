@@ -9,7 +9,8 @@ import torch
 import paper_1809_02390_amd as pkg
 import workloads as wl
 from oracle import lbm, measure
-from tests._gpu_helpers import (device_samples, lattice, oracle_init, params_pair, sampled_oracle)
+from tests._gpu_helpers import (crop_periodic, device_samples, lattice, oracle_init, params_pair,
+                                sampled_oracle)
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -158,6 +159,34 @@ def test_sampled_parity_spinodal_4096():
     assert np.abs(got - ref).max() / co.rho_l <= TOL
     tot = lat.moments(fields=False)
     assert tot[0] == pytest.approx(float(rho.sum()), rel=1e-6)
+
+
+def test_window_parity_spinodal_4096_late_times():
+    """The same workload run to t0 = 500 and t0 = 1900 (of its 2000 steps),
+    then 100-step windows: oracle runs on light-cone crops of the GPU state
+    at t0 (half-width 2 x 100 + 3: one step moves information two nodes,
+    streaming plus stencil) and is compared on the 5 x 5 nodes around each
+    crop's centre at t0 + 100.  Late windows see developed interfaces, with
+    velocities and gradients far from the initial noise."""
+    n, window = 4096, 100
+    _, co = params_pair(n, n, tr=0.7, width=10.0)
+    rho = wl.spinodal(co, n=n)
+    lat = lattice(n, n, rho, tr=0.7, width=10.0)
+    half = 2 * window + 3
+    centres = {500: [(1500, 2600), (4095, 0)], 1900: [(300, 3333)]}
+    for t0 in (500, 1900):
+        lat.step(t0 - lat.time)
+        st = lat.state()
+        crops = [crop_periodic(st, cx, cy, half).double().cpu().numpy() for cx, cy in centres[t0]]
+        del st
+        lat.step(window)
+        st = lat.state()
+        for (cx, cy), crop in zip(centres[t0], crops):
+            ref = lbm.run(crop, co, window, lbm.collide_sequence)[:, half - 2:half + 3, half - 2:half + 3]
+            got = crop_periodic(st, cx, cy, 2).double().cpu().numpy()
+            err = np.abs(got - ref).max() / co.rho_l
+            assert err <= TOL, (t0, cx, cy, err)
+        del st
 
 
 def test_sampled_parity_coalescence_16384x8192():
