@@ -182,7 +182,12 @@ def test_window_parity_spinodal_4096_late_times():
         lat.step(window)
         st = lat.state()
         for (cx, cy), crop in zip(centres[t0], crops):
-            ref = lbm.run(crop, co, window, lbm.collide_sequence)[:, half - 2:half + 3, half - 2:half + 3]
+            # the crop's own periodic seam is not the lattice's: it may blow
+            # up, but it lies 201 nodes from the compared ones, outside the
+            # 200-node reach of 100 steps
+            with np.errstate(over="ignore", invalid="ignore", divide="ignore"):
+                ref = lbm.run(crop, co, window, lbm.collide_sequence)[:, half - 2:half + 3, half - 2:half + 3]
+            assert np.all(np.isfinite(ref))
             got = crop_periodic(st, cx, cy, 2).double().cpu().numpy()
             err = np.abs(got - ref).max() / co.rho_l
             assert err <= TOL, (t0, cx, cy, err)
