@@ -19,6 +19,8 @@ Prints one JSON line:
                      adjoint kernel's own roofline, and the gradient error of
                      the 512^2 droplet-to-ellipse problem (2000 steps, K = 100)
                      against exact oracle derivatives stored in tests/golden;
+  legs.fwd_adjoint_keep_all_states  the same crop keeping all 1000 states
+                     in HBM (151 GB), so the backward recomputes nothing;
   cpu_baseline       the FP64 oracle timed on a bounded crop.
 """
 from __future__ import annotations
@@ -118,8 +120,14 @@ def coexistence_leg(pkg, wl, storage, tr=0.7, width=10.0, ny=128, steps=20000):
 
 
 def fwd_adjoint_leg(pkg, wl, timer, torch, n=2048, steps=1000, every=100):
-    """Checkpointed forward + adjoint of the droplet-pair crop, whole job."""
+    """Checkpointed forward + adjoint of the droplet-pair crop, whole job
+    (every = 1 keeps every state: no recomputation)."""
     tr, width = 0.6, 10.0
+    need = (steps // every + every + 4) * 36 * n * n
+    torch.cuda.empty_cache()
+    free = torch.cuda.mem_get_info()[0]
+    if need > 0.9 * free:
+        return {"skipped": f"needs {need / 2**30:.1f} GiB of device memory, {free / 2**30:.1f} GiB free"}
     d = pkg.lbm_derive(pkg.make_params(n, n, tr=tr, width=width))
     rho0 = wl.coalescence({"rho_g": d.rho_g, "rho_l": d.rho_l, "width": width}, nx=n, ny=n)
     r = pkg.Rollout(n, n, steps, every, tr=tr, width=width)
@@ -260,6 +268,7 @@ def main():
             legs[st] = leg
         legs["fp32_coexistence"] = coexistence_leg(pkg, wl, "fp32")
         legs["fwd_adjoint"] = fwd_adjoint_leg(pkg, wl, timer, torch)
+        legs["fwd_adjoint_keep_all_states"] = fwd_adjoint_leg(pkg, wl, timer, torch, every=1)
         legs["fwd_adjoint"]["adjoint_kernel"] = adjoint_kernel_leg(pkg, wl, timer, torch)
         legs["fwd_adjoint"]["gradient"] = gradient_error(pkg, wl, timer, torch)
 

@@ -8,17 +8,23 @@ The map differentiated is
 with the parameters sigma, W and T_r entering through theta = (G'^2, K', R T)
 of the self-tuning EOS (main Eqs. 20-23).
 
-Forward: the library state is saved every ``every`` steps (lbm_save_state).
-Backward: from the last segment to the first, the segment's states are
-recomputed from its checkpoint with lbm_step_saved (the same kernel as
-lbm_step, so bit for bit the forward's states) and the adjoint steps run back
-through them; lbm_adjoint_init closes with dL/d rho0, and
+Forward: f(0) is saved once (lbm_save_state); the steps then run from
+checkpoint buffer to checkpoint buffer (lbm_step_saved_chain, the kernel of
+lbm_step), keeping the state of every ``every``-th step and passing the
+others through two scratch buffers.  Backward: from the last segment to the
+first, the segment's states are recomputed from its checkpoint (bit for bit
+the forward's) and the adjoint steps run back through them
+(lbm_adjoint_run); lbm_adjoint_init closes with dL/d rho0, and
 
     dL/d(sigma, W, T_r) = J^T dL/d theta,   J = lbm_param_jacobian.
 
-Device memory: ceil(n / every) checkpoints + (every - 1) segment states + two
-adjoint states (11 planes each), all FP32 over nx*ny nodes.  Every step of
-the path runs in the HIP library; this module only orders the calls.
+Device memory: ceil(n / every) + 1 checkpoints + (every - 1) segment states
++ two adjoint states (11 planes each), all FP32 over nx*ny nodes.  With
+every = 1 every state is kept and nothing is recomputed (the forward +
+adjoint then moves 72 + 124 instead of 72 + 72 + 124 bytes per node and
+step; at 2048^2 x 1000 steps that is 151 GB of checkpoints, which HBM3E
+holds).  Every step of the path runs in the HIP library; this module only
+orders the calls.
 """
 from __future__ import annotations
 
@@ -38,8 +44,8 @@ class Rollout:
         self.lat = Lattice(nx, ny, device=device, **kw)
         self.nx, self.ny, self.nsteps, self.every = nx, ny, int(nsteps), int(every)
         self.starts = list(range(0, self.nsteps, self.every))
-        self.ckpt = [None] * len(self.starts)
-        self.pool = []  # segment states beyond the checkpoint
+        self.ckpt = [None] * (len(self.starts) + 1)  # states at the starts, then the final state
+        self.pool = []  # segment states beyond the checkpoint (forward: the two scratch buffers)
         self.inputs = None
 
     def _conv(self, a):
@@ -48,14 +54,24 @@ class Rollout:
         return torch.as_tensor(a).to(device=self.lat.f_a.device, dtype=torch.float32).reshape(
             self.ny, self.nx).contiguous()
 
+    def _buffer(self, k):
+        while len(self.pool) <= k:
+            self.pool.append(self.lat.checkpoint_buffer())
+        return self.pool[k]
+
     def forward(self, rho0, ux0=None, uy0=None):
         """rho_T (ny, nx) float32 after nsteps steps from f^eq(rho0)."""
         lat = self.lat
         self.inputs = (self._conv(rho0), self._conv(ux0), self._conv(uy0))
         lat.init(*self.inputs)
+        self.ckpt[0] = lat.save_state(self.ckpt[0])
         for s, t0 in enumerate(self.starts):
-            self.ckpt[s] = lat.save_state(self.ckpt[s])
-            lat.step(min(self.every, self.nsteps - t0))
+            m = min(self.every, self.nsteps - t0)
+            if self.ckpt[s + 1] is None:
+                self.ckpt[s + 1] = lat.checkpoint_buffer()
+            chain = [self.ckpt[s]] + [self._buffer(j % 2) for j in range(m - 1)] + [self.ckpt[s + 1]]
+            lat.step_saved_chain(chain)
+        lat.load_state(self.ckpt[-1], self.nsteps)
         return lat.moments()[0]
 
     def _segment_states(self, s):
@@ -95,7 +111,7 @@ class Rollout:
         return drho0, dth, dp
 
     def release(self):
-        self.ckpt = [None] * len(self.starts)
+        self.ckpt = [None] * (len(self.starts) + 1)
         self.pool = []
         self.lat.close()
 
