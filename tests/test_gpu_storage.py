@@ -118,3 +118,46 @@ def test_sampled_parity_spinodal_4096(storage):
     ref = sampled_oracle(co, rho, pts, steps)
     got = device_samples(lat.state(), pts)
     assert np.abs(got - ref).max() / co.rho_l <= STEP_TOL[storage]
+
+
+def test_domain_length_matches_fp32_spinodal_4096():
+    """Spinodal decomposition on 4096^2 (T_r = 0.7) for 2000 steps: the
+    domain length L(t) = 2 pi sum S(k) / sum |k| S(k) of the 2-byte runs
+    stays within 1e-3 of the FP32 one at t = 500, 1000, 2000 (L is a ratio of
+    spectral sums of the density; node-wise differences of the order of the
+    storage tolerance, <= 1e-3 of rho_l - rho_g, move it by less)."""
+    n = 4096
+    _, co = params_pair(n, n, tr=0.7, width=10.0)
+    rho = wl.spinodal(co, n=n)
+    curves = {}
+    for st in ["fp32"] + STORAGES:
+        lat = lattice(n, n, rho, tr=0.7, width=10.0, storage=st)
+        curves[st] = []
+        for t in (500, 1000, 2000):
+            lat.step(t - lat.time)
+            curves[st].append(measure.domain_length(lat.moments()[0].double().cpu().numpy()))
+        lat.close()
+    for st in STORAGES:
+        rel = np.abs(np.array(curves[st]) / np.array(curves["fp32"]) - 1).max()
+        assert rel <= 1e-3, (st, curves)
+    assert curves["fp32"][-1] > 1.3 * curves["fp32"][0]  # the domains coarsen
+
+
+@pytest.mark.parametrize("storage", STORAGES)
+def test_sampled_parity_coalescence_16384x8192(storage):
+    """Largest workload (two R = 400 droplets 20 nodes apart, T_r = 0.6) in
+    2-byte storage: sampled nodes after 5 steps against oracle crops."""
+    nx, ny, steps = 16384, 8192, 5
+    _, co = params_pair(nx, ny, tr=0.6, width=10.0)
+    rho = wl.coalescence(co, nx, ny)
+    lat = lattice(nx, ny, rho, tr=0.6, width=10.0, storage=storage)
+    lat.step(steps)
+    cx = nx // 2
+    pts = [(cx, ny // 2), (cx - 10, ny // 2), (cx - 410 - 400, ny // 2), (cx + 410, ny // 2 + 400), (0, 0),
+           (nx - 1, ny - 1)]
+    ref = sampled_oracle(co, rho, pts, steps)
+    st = lat.state()
+    got = device_samples(st, pts)
+    del st
+    lat.close()
+    assert np.abs(got - ref).max() / co.rho_l <= STEP_TOL[storage]
