@@ -40,6 +40,13 @@ struct Coef {
   T s_e, kq2, s_eps, s_p;  // kq2 = k (s_e/2 - 1) s_eps
   T q1, q7;                // (s_e - kq2) G'^2 / 2 and s_p G'^2 / 12
   T q2, s_q;               // s_eps G'^2 / 2 and s_q
+  // collide_scaled: the rows of m-bar - m times the diagonal of M^-1 = M^T D
+  // (1/36 for e, eps; 1/12 for q; 1/4 for p_xx, p_xy) with the sign of the
+  // corrections, folded into one constant per term
+  T w_r11, w_r17, w_r18, w_t1a, w_x1, w_t1b, w_q1;  // row e:   -cR../36, -cT1a/36, -cX1/36, cT1b/36, q1/36
+  T w_seps, w_q2, w_sq;                             // rows eps, q: s_eps/36, q2/36, s_q/12
+  T w_r71, w_r77, w_t7, w_x7, w_t7b, w_q7;          // row p_xx: -cR../4, -cT7/4, -cX7/4, -cT7 2b/4, q7/4
+  T w_r81, w_r88, w_x8, w_t8;                       // row p_xy: -cR../4, -cX8/4, -cT8/4
 };
 
 // Reciprocal: the one-instruction v_rcp_f32 (1 ulp) on the device, a
@@ -225,15 +232,80 @@ __host__ __device__ __forceinline__ void collide_delta(const T* m, const NodeSta
   dm[8] = T(2) * ((D8 - d8) + hF8) - corr8 + c.q7 * (gx * gy);
 }
 
+// The same collision as collide_delta, returned as w = D dm, the moment
+// change already scaled by the diagonal of M^-1 = M^T D (so f-bar = f + M^T w):
+// the scalings and the signs of the corrections are folded into the
+// w_* constants, and the cubic velocity monomials u_x^3, u_y^3, u_x u_y^2,
+// u_x^2 u_y are formed once for the force moments and for the T and X terms
+// (T . g + dp X . g collapses to one coefficient per monomial and row).
+// Rows 3 and 5 are F/6.  Same arithmetic as collide_delta up to rounding.
+template <typename T>
+__host__ __device__ __forceinline__ void collide_scaled(const T* m, const NodeState<T>& s, T gx, T gy,
+                                                        const Coef<T>& c, T* w) {
+  const T rho = s.rho, ux = s.ux, uy = s.uy, Fx = s.Fx, Fy = s.Fy, dp = s.dp_lbe;
+  const T ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy, u2 = ux2 + uy2, dxy = ux2 - uy2;
+  const T c3x = ux * ux2, c3y = uy * uy2, cxyy = uxy * uy, cxxy = uxy * ux;
+  // equilibrium moments (main Eq. 3) and half force moments (main Eq. 4)
+  const T meq1 = T(2) * (s.eta - rho) + T(3) * rho * u2;
+  const T meq2 = c.alpha2 * rho + c.beta2 * s.eta + rho * (T(9) * ux2 * uy2 - T(3) * u2);
+  const T meq4 = rho * (T(3) * cxyy - ux), meq6 = rho * (T(3) * cxxy - uy);
+  const T meq7 = rho * dxy, meq8 = rho * uxy;
+  const T Fxu = Fx * ux, Fyu = Fy * uy;
+  const T Fu3 = T(3) * (Fxu + Fyu);
+  const T hF2 = T(9) * (Fx * cxyy + Fy * cxxy) - Fu3;
+  const T hF4 = T(1.5) * (Fx * uy2 + T(2) * Fy * uxy) - T(0.5) * Fx;
+  const T hF6 = T(1.5) * (Fy * ux2 + T(2) * Fx * uxy) - T(0.5) * Fy;
+  const T hF7 = Fxu - Fyu;
+  const T hF8 = T(0.5) * (Fx * uy + Fy * ux);
+  // (1) d = m - m^eq + F_m/2
+  const T d1 = m[1] - meq1 + Fu3, d2 = m[2] - meq2 + hF2, d4 = m[4] - meq4 + hF4;
+  const T d6 = m[6] - meq6 + hF6, d7 = m[7] - meq7 + hF7, d8 = m[8] - meq8 + hF8;
+  // (2)-(3) D = (1 - s/2)(d + N d)
+  const T D1 = c.om_e * (d1 + c.k_seps_h * d2 + c.h_sq_h * (ux * d4 + uy * d6));
+  const T D7 = c.om_p * (d7 + c.b_sq * (ux * d4 - uy * d6));
+  const T D8 = c.om_p * (d8 + c.b_sq_h * (uy * d4 + ux * d6));
+  // (4) corrections with (5) m-bar - m = 2 (D - d + F_m/2) - corrections and
+  // (6) S Q_m, each row times its factor of D
+  const T gg = gx * gx + gy * gy;
+  const T b1 = dp * c.w_x1 + c.w_t1b, b7 = dp * c.w_x7 + c.w_t7b, b8 = dp * c.w_x8 + c.w_t8;
+  w[1] = T(2.0 / 36.0) * ((D1 - d1) + Fu3) + c.w_r11 * u2 * D1 + c.w_r17 * dxy * D7 + c.w_r18 * uxy * D8 +
+         (c.w_t1a * c3x + b1 * cxyy) * gx + (c.w_t1a * c3y + b1 * cxxy) * gy + c.w_q1 * gg;
+  w[2] = T(2.0 / 36.0) * hF2 - c.w_seps * d2 - c.w_q2 * gg;
+  w[4] = T(1.0 / 6.0) * hF4 - c.w_sq * d4;
+  w[6] = T(1.0 / 6.0) * hF6 - c.w_sq * d6;
+  w[7] = T(0.5) * ((D7 - d7) + hF7) + c.w_r71 * dxy * D1 + c.w_r77 * u2 * D7 +
+         (c.w_t7 * c3x + b7 * cxyy) * gx - (c.w_t7 * c3y + b7 * cxxy) * gy + c.w_q7 * (gx * gx - gy * gy);
+  w[8] = T(0.5) * ((D8 - d8) + hF8) + c.w_r81 * uxy * D1 + c.w_r88 * u2 * D8 +
+         b8 * ((c3y + T(2) * cxxy) * gx + (c3x + T(2) * cxyy) * gy) + c.w_q7 * (gx * gy);
+  w[3] = Fx * T(1.0 / 6.0);
+  w[5] = Fy * T(1.0 / 6.0);
+}
+
+// f += M^T w (w = D dm from collide_scaled, w_0 = 0).
+template <typename T>
+__host__ __device__ __forceinline__ void add_transpose_moments(const T* w, T* f) {
+  const T A = -(w[1] + T(2) * w[2]), X = w[3] - T(2) * w[4], Y = w[5] - T(2) * w[6];
+  f[0] += T(4) * (w[2] - w[1]);
+  f[1] += (A + w[7]) + X;
+  f[3] += (A + w[7]) - X;
+  f[2] += (A - w[7]) + Y;
+  f[4] += (A - w[7]) - Y;
+  const T D = T(2) * w[1] + w[2], P = w[3] + w[4], Q = w[5] + w[6];
+  f[5] += (D + w[8]) + (P + Q);
+  f[7] += (D + w[8]) - (P + Q);
+  f[6] += (D - w[8]) + (Q - P);
+  f[8] += (D - w[8]) - (Q - P);
+}
+
 // f-bar from pre-collision f at one node of density rho (density(f)), given
 // the stencil gradient g.
 template <typename T>
 __host__ __device__ __forceinline__ void collide_node(T* f, T rho, T gx, T gy, const Coef<T>& c) {
-  T m[9], dm[9];
+  T m[9], w[9];
   forward_moments(f, m);
   const NodeState<T> s = node_state(rho, m[3], m[5], gx, gy, c);
-  collide_delta(m, s, gx, gy, c, dm);
-  add_inverse_moments(dm, s.Fx, s.Fy, f);
+  collide_scaled(m, s, gx, gy, c, w);
+  add_transpose_moments(w, f);
 }
 
 // Equilibrium populations f^eq = M^-1 m^eq(rho, u, eta(rho)).

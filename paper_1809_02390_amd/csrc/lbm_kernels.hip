@@ -814,6 +814,12 @@ Coef<float> make_coef(const lbm_derived& d, double varpi, double a, double b) {
   c.q7 = sp * d.g2 / 12.0;
   c.q2 = seps * 0.5 * d.g2;
   c.s_q = sq;
+  c.w_r11 = -c.cR11 / 36.0, c.w_r17 = -c.cR17 / 36.0, c.w_r18 = -c.cR18 / 36.0;
+  c.w_t1a = -c.cT1a / 36.0, c.w_x1 = -c.cX1 / 36.0, c.w_t1b = c.cT1b / 36.0, c.w_q1 = c.q1 / 36.0;
+  c.w_seps = seps / 36.0, c.w_q2 = c.q2 / 36.0, c.w_sq = sq / 12.0;
+  c.w_r71 = -c.cR71 / 4.0, c.w_r77 = -c.cR77 / 4.0, c.w_t7 = -c.cT7 / 4.0, c.w_x7 = -c.cX7 / 4.0;
+  c.w_t7b = -c.cT7 * c.two_b / 4.0, c.w_q7 = c.q7 / 4.0;
+  c.w_r81 = -c.cR81 / 4.0, c.w_r88 = -c.cR88 / 4.0, c.w_x8 = -c.cX8 / 4.0, c.w_t8 = -c.cT8 / 4.0;
   Coef<float> f;
   const double* src = reinterpret_cast<const double*>(&c);
   float* dstp = reinterpret_cast<float*>(&f);
