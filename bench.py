@@ -21,6 +21,7 @@ Prints one JSON line:
                      against exact oracle derivatives stored in tests/golden;
   legs.fwd_adjoint_keep_all_states  the same crop keeping all 1000 states
                      in HBM (151 GB), so the backward recomputes nothing;
+  legs.coalescence_16384x8192  the step on the largest workload, each storage;
   cpu_baseline       the FP64 oracle timed on a bounded crop.
 """
 from __future__ import annotations
@@ -104,6 +105,21 @@ def step_leg(pkg, wl, timer, storage, n, steps, warmup, tr=0.7, width=10.0):
                      "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                      "algorithmic_bytes_per_lu": BYTES_PER_LU[storage],
                      "traffic": measured_traffic("step_" + storage.replace("fp", "f"), n * n)}
+
+
+def coalescence_leg(pkg, wl, timer, storage, nx=16384, ny=8192, steps=200, warmup=20):
+    """The largest workload: two R = 400 droplets 20 nodes apart on
+    16384 x 8192 at T/T_c = 0.6 (9.7 GB of FP32 A/B buffers)."""
+    d = pkg.lbm_derive(pkg.make_params(nx, ny, tr=0.6, width=10.0))
+    rho0 = wl.coalescence({"rho_g": d.rho_g, "rho_l": d.rho_l, "width": 10.0}, nx, ny)
+    lat = pkg.Lattice(nx, ny, tr=0.6, width=10.0, storage=storage).init(rho0)
+    lat.step(warmup)
+    ms = timer(lambda: lat.step(steps))
+    lat.close()
+    per = ms / steps
+    gbs = BYTES_PER_LU[storage] * nx * ny / (per * 1e-3) / 1e9
+    return {"mlups": round(nx * ny * steps / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(per, 4),
+            "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def coexistence_leg(pkg, wl, storage, tr=0.7, width=10.0, ny=128, steps=20000):
@@ -267,6 +283,7 @@ def main():
             leg["coexistence"] = coexistence_leg(pkg, wl, st)
             legs[st] = leg
         legs["fp32_coexistence"] = coexistence_leg(pkg, wl, "fp32")
+        legs["coalescence_16384x8192"] = {st: coalescence_leg(pkg, wl, timer, st) for st in ("fp32", "fp16", "bf16")}
         legs["fwd_adjoint"] = fwd_adjoint_leg(pkg, wl, timer, torch)
         legs["fwd_adjoint_keep_all_states"] = fwd_adjoint_leg(pkg, wl, timer, torch, every=1)
         legs["fwd_adjoint"]["adjoint_kernel"] = adjoint_kernel_leg(pkg, wl, timer, torch)

@@ -162,8 +162,8 @@ def test_sampled_parity_spinodal_4096():
 
 
 def test_window_parity_spinodal_4096_late_times():
-    """The same workload run to t0 = 500 and t0 = 1900 (of its 2000 steps),
-    then 100-step windows: oracle runs on light-cone crops of the GPU state
+    """The same workload over its 2000 steps, in 100-step windows starting at
+    t0 = 0, 500, 1000, 1500 and 1900: oracle runs on light-cone crops of the GPU state
     at t0 (half-width 2 x 100 + 3: one step moves information two nodes,
     streaming plus stencil) and is compared on the 5 x 5 nodes around each
     crop's centre at t0 + 100.  Late windows see developed interfaces, with
@@ -173,8 +173,9 @@ def test_window_parity_spinodal_4096_late_times():
     rho = wl.spinodal(co, n=n)
     lat = lattice(n, n, rho, tr=0.7, width=10.0)
     half = 2 * window + 3
-    centres = {500: [(1500, 2600), (4095, 0)], 1900: [(300, 3333)]}
-    for t0 in (500, 1900):
+    centres = {0: [(2047, 2048)], 500: [(1500, 2600), (4095, 0)], 1000: [(3000, 700)], 1500: [(9, 2222)],
+               1900: [(300, 3333)]}
+    for t0 in sorted(centres):
         lat.step(t0 - lat.time)
         st = lat.state()
         crops = [crop_periodic(st, cx, cy, half).double().cpu().numpy() for cx, cy in centres[t0]]
@@ -192,6 +193,41 @@ def test_window_parity_spinodal_4096_late_times():
             err = np.abs(got - ref).max() / co.rho_l
             assert err <= TOL, (t0, cx, cy, err)
         del st
+
+
+def test_window_parity_droplet_256():
+    """The 256^2 Laplace droplet (R = 40, T_r = 0.8, W = 10) over 20000
+    steps: from the GPU state at t0 = 2000, 10000 and 19900, 100 oracle
+    steps on the whole periodic lattice against the GPU's next 100 steps."""
+    n = 256
+    _, co = params_pair(n, n, tr=0.8, width=10.0)
+    lat = lattice(n, n, wl.static_droplet(co, n, 40.0), tr=0.8, width=10.0)
+    for t0 in (2000, 10000, 19900):
+        lat.step(t0 - lat.time)
+        f0 = lat.state().double().cpu().numpy()
+        lat.step(100)
+        compare(lat, lbm.run(f0, co, 100, lbm.collide_sequence), co)
+
+
+def test_window_parity_coalescence_16384x8192():
+    """Largest workload, 100-step window from t0 = 1000 on a light-cone crop
+    through the gap between the droplets."""
+    nx, ny, t0, window = 16384, 8192, 1000, 100
+    _, co = params_pair(nx, ny, tr=0.6, width=10.0)
+    lat = lattice(nx, ny, wl.coalescence(co, nx, ny), tr=0.6, width=10.0)
+    lat.step(t0)
+    half, c = 2 * window + 3, (nx // 2 - 7, ny // 2 + 30)  # in the gap, in the left droplet's interface
+    st = lat.state()
+    crop = crop_periodic(st, *c, half).double().cpu().numpy()
+    del st
+    lat.step(window)
+    st = lat.state()
+    got = crop_periodic(st, *c, 2).double().cpu().numpy()
+    del st
+    with np.errstate(over="ignore", invalid="ignore", divide="ignore"):  # crop seam, outside the light cone
+        ref = lbm.run(crop, co, window, lbm.collide_sequence)[:, half - 2:half + 3, half - 2:half + 3]
+    assert np.all(np.isfinite(ref))
+    assert np.abs(got - ref).max() / co.rho_l <= TOL
 
 
 def test_sampled_parity_coalescence_16384x8192():
