@@ -22,6 +22,8 @@ Prints one JSON line:
   legs.fwd_adjoint_keep_all_states  the same crop keeping all 1000 states
                      in HBM (151 GB), so the backward recomputes nothing;
   legs.coalescence_16384x8192  the step on the largest workload, each storage;
+  legs.elliptic_droplet  oscillation period of the paper's elliptic droplet
+                     against the linear capillary mode;
   cpu_baseline       the FP64 oracle timed on a bounded crop.
 """
 from __future__ import annotations
@@ -120,6 +122,35 @@ def coalescence_leg(pkg, wl, timer, storage, nx=16384, ny=8192, steps=200, warmu
     gbs = BYTES_PER_LU[storage] * nx * ny / (per * 1e-3) / 1e9
     return {"mlups": round(nx * ny * steps / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(per, 4),
             "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def ellipse_leg(pkg, wl, n=512, tr=0.6, width=10.0, s_p=1.4, every=100, nsamp=600):
+    """Oscillation of an elliptic droplet (semi-axes 96.0 and 42.7): period
+    from the late zero crossings of a_x - a_y against the linear capillary
+    mode n = 2, omega^2 = 6 sigma / ((rho_l + rho_g) R^3)."""
+    d = pkg.lbm_derive(pkg.make_params(n, n, tr=tr, width=width, s_p=s_p))
+    rho0 = wl.ellipse(n, n, d.rho_g, d.rho_l, width, (n / 2, n / 2), 96.0, 42.7)
+    lat = pkg.Lattice(n, n, tr=tr, width=width, s_p=s_p).init(rho0)
+    level = 0.5 * (d.rho_l + d.rho_g)
+
+    def semi(pr):
+        i = np.where(pr > level)[0]
+        a, b = i.min(), i.max()
+        return 0.5 * ((b + (pr[b] - level) / (pr[b] - pr[b + 1])) - (a - (pr[a] - level) / (pr[a] - pr[a - 1])))
+
+    dev = []
+    for _ in range(nsamp):
+        lat.step(every)
+        r = lat.moments()[0].double().cpu().numpy()
+        dev.append(semi(r[n // 2]) - semi(r[:, n // 2]))
+    lat.close()
+    cross = [every * (i + 1) + every * dev[i] / (dev[i] - dev[i + 1]) for i in range(nsamp - 1)
+             if (dev[i] > 0) != (dev[i + 1] > 0)]
+    period = 2 * float(np.mean(np.diff(cross)[-3:]))
+    analytic = 2 * np.pi * np.sqrt((d.rho_l + d.rho_g) * (96.0 * 42.7) ** 1.5 / (6 * d.sigma))
+    return {"workload": f"elliptic droplet 96.0 x 42.7 on {n}^2, T/Tc={tr}, W={width}, s_p={s_p}",
+            "period_steps": round(period, 1), "analytic_steps": round(float(analytic), 1),
+            "rel_err": round(period / analytic - 1, 5)}
 
 
 def coexistence_leg(pkg, wl, storage, tr=0.7, width=10.0, ny=128, steps=20000):
@@ -284,6 +315,7 @@ def main():
             legs[st] = leg
         legs["fp32_coexistence"] = coexistence_leg(pkg, wl, "fp32")
         legs["coalescence_16384x8192"] = {st: coalescence_leg(pkg, wl, timer, st) for st in ("fp32", "fp16", "bf16")}
+        legs["elliptic_droplet"] = ellipse_leg(pkg, wl)
         legs["fwd_adjoint"] = fwd_adjoint_leg(pkg, wl, timer, torch)
         legs["fwd_adjoint_keep_all_states"] = fwd_adjoint_leg(pkg, wl, timer, torch, every=1)
         legs["fwd_adjoint"]["adjoint_kernel"] = adjoint_kernel_leg(pkg, wl, timer, torch)
