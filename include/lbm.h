@@ -255,7 +255,8 @@ int64_t lbm_time(const lbm_ctx* ctx);
 /* Copy the derived coefficients of a context. */
 int lbm_get_derived(const lbm_ctx* ctx, lbm_derived* out);
 
-/* Destroy a context (frees its scratch; never the caller's buffers). */
+/* Destroy a context: frees its scratch on its device (waiting for its work
+ * in flight); never the caller's buffers. */
 void lbm_destroy(lbm_ctx* ctx);
 
 #ifdef __cplusplus

@@ -1011,7 +1011,7 @@ int lbm_create(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, void* r
   if (p->storage != LBM_FP32 && !rho_ref)
     return fail(LBM_EINVAL, "the 2-byte storages need the reference-density buffer rho_ref");
   lbm_ctx* c = new (std::nothrow) lbm_ctx{};
-  if (!c) return fail(LBM_EINVAL, "out of host memory");
+  if (!c) return fail(LBM_EHIP, "out of host memory");
   c->p = *p;
   c->d = d;
   c->c = make_coef(d, p->varpi, p->a, p->b);
@@ -1353,7 +1353,13 @@ int lbm_get_derived(const lbm_ctx* ctx, lbm_derived* out) {
 
 void lbm_destroy(lbm_ctx* ctx) {
   if (!ctx) return;
-  if (ctx->scratch) (void)hipFree(ctx->scratch);
+  if (ctx->scratch) {
+    int cur = -1;
+    const bool other = hipGetDevice(&cur) == hipSuccess && cur != ctx->device;
+    if (other) (void)hipSetDevice(ctx->device);
+    (void)hipFree(ctx->scratch);  // waits for the context's work in flight
+    if (other) (void)hipSetDevice(cur);
+  }
   delete ctx;
 }
 
