@@ -132,30 +132,6 @@ __host__ __device__ __forceinline__ void inverse_moments(const T* m, T* f) {
   f[0] = m[0] - (((f[1] + f[3]) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8])));
 }
 
-// f += M^-1 dm for a moment change with dm_0 = 0 (the collision conserves
-// mass), dm_3 = Fx and dm_5 = Fy (it adds the force to the momentum).  The
-// moving rows of M sum to zero, so the nine increments sum to zero up to the
-// rounding of their additions: no constant 1/9 enters and the node's mass
-// has no systematic drift.
-template <typename T>
-__host__ __device__ __forceinline__ void add_inverse_moments(const T* dm, T Fx, T Fy, T* f) {
-  const T w1 = dm[1] * T(1.0 / 36.0), w2 = dm[2] * T(1.0 / 36.0);
-  const T w3 = Fx * T(1.0 / 6.0), w4 = dm[4] * T(1.0 / 12.0);
-  const T w5 = Fy * T(1.0 / 6.0), w6 = dm[6] * T(1.0 / 12.0);
-  const T w7 = dm[7] * T(0.25), w8 = dm[8] * T(0.25);
-  const T A = -(w1 + T(2) * w2), X = w3 - T(2) * w4, Y = w5 - T(2) * w6;
-  f[0] += T(4) * (w2 - w1);
-  f[1] += (A + w7) + X;
-  f[3] += (A + w7) - X;
-  f[2] += (A - w7) + Y;
-  f[4] += (A - w7) - Y;
-  const T D = T(2) * w1 + w2, P = w3 + w4, Q = w5 + w6;
-  f[5] += (D + w8) + (P + Q);
-  f[7] += (D + w8) - (P + Q);
-  f[6] += (D - w8) + (Q - P);
-  f[8] += (D - w8) - (Q - P);
-}
-
 // Node-local quantities at time t: velocity with the half-force correction
 // (main Eq. 5), force F = G^2 rho g, and the pressure slope.
 template <typename T>
@@ -178,67 +154,16 @@ __host__ __device__ __forceinline__ NodeState<T> node_state(T rho, T jx, T jy, T
 }
 
 // Moment-space collision (supplement Eq. 1) by the six-step sequence of
-// supplement Sec. IV, as the change of the moments: dm = m-bar - m for the
-// pre-collision moments m (rows 1, 2, 4, 6, 7, 8; row 0 does not change and
-// rows 3, 5 gain Fx, Fy).  g is the stencil gradient (= grad rho, supplement
+// supplement Sec. IV, returned as the change of the moments m-bar - m for
+// the pre-collision moments m, already scaled by the diagonal of
+// M^-1 = M^T D: w = D (m-bar - m), so that f-bar = f + M^T w.  Row 0 does
+// not change (mass) and rows 3, 5 gain F (w = F/6); rows 1, 2, 4, 6, 7, 8
+// follow the six steps below.  The scalings and the signs of the correction
+// terms are folded into the w_* constants, and the cubic velocity monomials
+// u_x^3, u_y^3, u_x u_y^2, u_x^2 u_y are formed once for the force moments
+// and for the T and X terms (T . g + dp X . g is one coefficient per
+// monomial and row).  g is the stencil gradient (= grad rho, supplement
 // Eq. 61); grad p_LBE = dp_lbe g.
-template <typename T>
-__host__ __device__ __forceinline__ void collide_delta(const T* m, const NodeState<T>& s, T gx, T gy,
-                                                       const Coef<T>& c, T* dm) {
-  const T rho = s.rho, ux = s.ux, uy = s.uy, Fx = s.Fx, Fy = s.Fy, dp = s.dp_lbe;
-  const T ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy, u2 = ux2 + uy2, dxy = ux2 - uy2;
-  // equilibrium moments m^eq (main Eq. 3) and half force moments F_m/2 (main Eq. 4)
-  const T meq1 = T(2) * (s.eta - rho) + T(3) * rho * u2;
-  const T meq2 = c.alpha2 * rho + c.beta2 * s.eta + rho * (T(9) * ux2 * uy2 - T(3) * u2);
-  const T meq4 = rho * ux * (T(3) * uy2 - T(1));
-  const T meq6 = rho * uy * (T(3) * ux2 - T(1));
-  const T meq7 = rho * dxy;
-  const T meq8 = rho * uxy;
-  const T Fu3 = T(3) * (Fx * ux + Fy * uy);
-  const T hF1 = Fu3;
-  const T hF2 = T(9) * (Fx * ux * uy2 + Fy * uy * ux2) - Fu3;
-  const T hF4 = T(1.5) * (Fx * uy2 + T(2) * Fy * uxy) - T(0.5) * Fx;
-  const T hF6 = T(1.5) * (Fy * ux2 + T(2) * Fx * uxy) - T(0.5) * Fy;
-  const T hF7 = Fx * ux - Fy * uy;
-  const T hF8 = T(0.5) * (Fx * uy + Fy * ux);
-  // (1) d = m - m^eq + F_m/2
-  const T d1 = m[1] - meq1 + hF1, d2 = m[2] - meq2 + hF2, d4 = m[4] - meq4 + hF4;
-  const T d6 = m[6] - meq6 + hF6, d7 = m[7] - meq7 + hF7, d8 = m[8] - meq8 + hF8;
-  // (2) off-diagonal part of S, (3) diagonal relaxation: D = (1 - s/2)(d + N d)
-  const T D1 = c.om_e * (d1 + c.k_seps_h * d2 + c.h_sq_h * (ux * d4 + uy * d6));
-  const T D7 = c.om_p * (d7 + c.b_sq * (ux * d4 - uy * d6));
-  const T D8 = c.om_p * (d8 + c.b_sq_h * (uy * d4 + ux * d6));
-  // (4) cubic-velocity corrections; T . grad rho + X . grad p = (T + dp X) . g
-  const T R11 = c.cR11 * u2, R17 = c.cR17 * dxy, R18 = c.cR18 * uxy;
-  const T t1x = ux * (c.cT1a * ux2 - c.cT1b * uy2), t1y = uy * (c.cT1a * uy2 - c.cT1b * ux2);
-  const T x1x = c.cX1 * uxy * uy, x1y = c.cX1 * uxy * ux;
-  const T corr1 = R11 * D1 + R17 * D7 + R18 * D8 + (t1x + dp * x1x) * gx + (t1y + dp * x1y) * gy;
-  const T R71 = c.cR71 * dxy, R77 = c.cR77 * u2;
-  const T t7x = c.cT7 * ux * (ux2 + c.two_b * uy2), t7y = -c.cT7 * uy * (uy2 + c.two_b * ux2);
-  const T x7x = c.cX7 * uxy * uy, x7y = -c.cX7 * uxy * ux;
-  const T corr7 = R71 * D1 + R77 * D7 + (t7x + dp * x7x) * gx + (t7y + dp * x7y) * gy;
-  const T R81 = c.cR81 * uxy, R88 = c.cR88 * u2;
-  const T v8x = uy * (uy2 + T(2) * ux2), v8y = ux * (ux2 + T(2) * uy2);
-  const T corr8 = R81 * D1 + R88 * D8 + (c.cT8 + dp * c.cX8) * (v8x * gx + v8y * gy);
-  // (5) m-bar = m - 2 d + 2 F_m/2 + 2 D - corrections; rows 2, 4, 6 have no
-  //     coupling, so -2 d + 2 D = -s d there.  (6) adds S Q_m with
-  //     F-tilde = G g (main Eq. 14): Q_1 = -Q_2 = G^2 |g|^2 / 2.
-  const T gg = gx * gx + gy * gy;
-  dm[1] = T(2) * ((D1 - d1) + hF1) - corr1 + c.q1 * gg;
-  dm[2] = T(2) * hF2 - c.s_eps * d2 - c.q2 * gg;
-  dm[4] = T(2) * hF4 - c.s_q * d4;
-  dm[6] = T(2) * hF6 - c.s_q * d6;
-  dm[7] = T(2) * ((D7 - d7) + hF7) - corr7 + c.q7 * (gx * gx - gy * gy);
-  dm[8] = T(2) * ((D8 - d8) + hF8) - corr8 + c.q7 * (gx * gy);
-}
-
-// The same collision as collide_delta, returned as w = D dm, the moment
-// change already scaled by the diagonal of M^-1 = M^T D (so f-bar = f + M^T w):
-// the scalings and the signs of the corrections are folded into the
-// w_* constants, and the cubic velocity monomials u_x^3, u_y^3, u_x u_y^2,
-// u_x^2 u_y are formed once for the force moments and for the T and X terms
-// (T . g + dp X . g collapses to one coefficient per monomial and row).
-// Rows 3 and 5 are F/6.  Same arithmetic as collide_delta up to rounding.
 template <typename T>
 __host__ __device__ __forceinline__ void collide_scaled(const T* m, const NodeState<T>& s, T gx, T gy,
                                                         const Coef<T>& c, T* w) {
@@ -369,8 +294,8 @@ __host__ __device__ __forceinline__ void transpose_moments(const T* a, T* f) {
 // populations f, the stencil gradient g and lam = dL/d f-bar, returns
 // lam_f = dL/d f (at fixed g), a_g = dL/d g, and adds dL/d(G'^2, K', R T)
 // to a_th.  The forward quantities are recomputed here; the sweep visits the
-// assignments of collide_node / collide_delta / node_state / eos in
-// reverse order (differentiating m-bar = m + dm).
+// assignments of collide_node / collide_scaled / node_state / eos in
+// reverse order, written for the unscaled moments (m-bar = m + D^-1 w).
 template <typename T>
 __host__ __device__ __forceinline__ void collide_node_vjp(const T* f, T gx, T gy, const Coef<T>& c, const T* lam,
                                                           T* lam_f, T& a_gx, T& a_gy, T* a_th) {
@@ -426,7 +351,7 @@ __host__ __device__ __forceinline__ void collide_node_vjp(const T* f, T gx, T gy
   T a_rho = l[0], a_ux = 0, a_uy = 0, a_Fx = l[3], a_Fy = l[5], a_dp = 0, a_eta = 0, a_g2 = 0;
   T a_m[9] = {0, 0, 0, l[3], 0, l[5], 0, 0, 0};
   a_gx = 0, a_gy = 0;
-  // post-collision rows (see collide_delta steps (5)-(6))
+  // post-collision rows (collide_scaled steps (5)-(6))
   T a_meq1 = l[1], a_hF1 = l[1], a_d1 = -l[1], a_D1 = T(2) * l[1], a_c1 = -l[1];
   T a_gg = c.q1 * l[1] - c.s_eps * T(0.5) * c.g2 * l[2];
   a_g2 += T(0.5) * (c.s_e - c.kq2) * gg * l[1] - c.s_eps * T(0.5) * gg * l[2];
