@@ -205,11 +205,25 @@ struct TileShape {
   static_assert(NRING <= NTHREADS, "one ring node per thread");
 };
 
-// Tile of the step kernel (TX, TY, WY); a compile-time tuning knob.
-#ifndef LBM_STEP_TILE
-#define LBM_STEP_TILE 128, 8, 4
+// Tiles of the step kernel (TX, TY, WY), per storage; compile-time tuning
+// knobs.  FP32 (bound by HBM): 256 x 8 in 1024-thread workgroups, 2-byte
+// storages (bound by the vector ALU): 128 x 8 in 512.
+#ifndef LBM_STEP_TILE_F32
+#define LBM_STEP_TILE_F32 256, 8, 4
 #endif
-using StepTile = TileShape<LBM_STEP_TILE>;
+#ifndef LBM_STEP_TILE_16
+#define LBM_STEP_TILE_16 128, 8, 4
+#endif
+template <class St>
+struct StepTileOf {
+  using type = TileShape<LBM_STEP_TILE_16>;
+};
+template <>
+struct StepTileOf<StoreF32> {
+  using type = TileShape<LBM_STEP_TILE_F32>;
+};
+template <class St>
+using StepTile = typename StepTileOf<St>::type;
 using MomTile = TileShape<64, 16, 4>;
 
 // Tile order across the eight XCDs of the chip: workgroups are dealt to the
@@ -932,18 +946,33 @@ namespace {
 template <class S>
 int tiles_x(int nx) { return (nx + S::TX - 1) / S::TX; }
 
-// Tile columns per strip of the tile order (strip_tile).  Measured on
-// MI355X for the FP32 step and the adjoint, which stream their bytes from
-// HBM: raster order up to 16 tile columns (2048 nodes), strips of a quarter
-// of the tile columns (at least 8) beyond (4096^2: strips of 8, +5 %;
-// 16384 x 8192: strips of 32, +13 % over raster).  The 2-byte steps, bound
-// by the vector ALU, keep raster order (one strip).
-int strip_width(int ntx, bool raster) {
-  if (raster || ntx <= 16) return ntx;
-  return ntx / 4 < 8 ? 8 : ntx / 4;
+// Tile columns per strip of the tile order (strip_tile) for tiles tx nodes
+// wide on a lattice nx nodes wide.  Measured on MI355X for the FP32 step and
+// the adjoint, which stream their bytes from HBM: raster order up to 2048
+// nodes, beyond that strips a quarter of the lattice wide and at least 1024
+// nodes (4096^2: 1024-node strips, +5 %; 16384 x 8192: 4096-node strips,
+// +13 % over raster).  The 2-byte steps, bound by the vector ALU, keep
+// raster order (one strip).
+int strip_width(int nx, int tx, bool raster) {
+  const int ntx = (nx + tx - 1) / tx;
+  if (raster || nx <= 2048) return ntx;
+  const int nodes = nx / 4 < 1024 ? 1024 : nx / 4;
+  const int w = nodes / tx;
+  return w < 1 ? 1 : (w > ntx ? ntx : w);
 }
 template <class S>
 int tiles_total(int nx, int ny) { return tiles_x<S>(nx) * ((ny + S::TY - 1) / S::TY); }
+
+// One step of storage St from the buffer src (and its reference plane) to
+// dst, on the context's stream.
+template <class St>
+void launch_step(const lbm_ctx* ctx, const void* src, void* dst, const uint16_t* ref_in, uint16_t* ref_out) {
+  using S = StepTile<St>;
+  const int nx = ctx->p.nx, ny = ctx->p.ny;
+  step_kernel<S, St><<<tiles_total<S>(nx, ny), dim3(S::TX, S::WY), 0, ctx->stream>>>(
+      src, dst, ref_in, ref_out, nx, ny, tiles_x<S>(nx), tiles_total<S>(nx, ny),
+      strip_width(nx, S::TX, St::kRef), ctx->c, ctx->q);
+}
 
 int check_ctx(const lbm_ctx* ctx, bool need_state) {
   if (!ctx) return fail(LBM_EINVAL, "context is NULL");
@@ -1114,16 +1143,11 @@ int lbm_step(lbm_ctx* ctx, int32_t n) {
   if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
   if (n == 0) return LBM_OK;
   if (int st = set_device(ctx)) return st;
-  using S = StepTile;
-  const int ntx = tiles_x<S>(ctx->p.nx), ntiles = tiles_total<S>(ctx->p.nx, ctx->p.ny);
-  const int strip = strip_width(ntx, ctx->p.storage != LBM_FP32);
-  const dim3 block(S::TX, S::WY);
   int st = with_storage(ctx, [&](auto store) -> int {
     using St = decltype(store);
     for (int32_t s = 0; s < n; ++s) {
       const int a = ctx->cur, b = ctx->cur ^ 1;
-      step_kernel<S, St><<<ntiles, block, 0, ctx->stream>>>(ctx->buf[a], ctx->buf[b], ctx->ref[a], ctx->ref[b],
-                                                            ctx->p.nx, ctx->p.ny, ntx, ntiles, strip, ctx->c, ctx->q);
+      launch_step<St>(ctx, ctx->buf[a], ctx->buf[b], ctx->ref[a], ctx->ref[b]);
       ctx->cur = b;
     }
     HIP_OK(hipGetLastError());
@@ -1203,11 +1227,7 @@ int lbm_step_saved(lbm_ctx* ctx, const void* src, void* dst) {
   if (int st = need_fp32(ctx, "lbm_step_saved")) return st;
   if (!src || !dst || src == dst) return fail(LBM_EINVAL, "src and dst must be two distinct device buffers");
   if (int st = set_device(ctx)) return st;
-  using S = StepTile;
-  const int ntx = tiles_x<S>(ctx->p.nx);
-  step_kernel<S, StoreF32><<<tiles_total<S>(ctx->p.nx, ctx->p.ny), dim3(S::TX, S::WY), 0, ctx->stream>>>(
-      src, dst, nullptr, nullptr, ctx->p.nx, ctx->p.ny, ntx, tiles_total<S>(ctx->p.nx, ctx->p.ny),
-      strip_width(ntx, false), ctx->c, ctx->q);
+  launch_step<StoreF32>(ctx, src, dst, nullptr, nullptr);
   HIP_OK(hipGetLastError());
   return LBM_OK;
 }
@@ -1222,12 +1242,7 @@ int lbm_step_saved_chain(lbm_ctx* ctx, void* const* bufs, int32_t n) {
     if (!bufs[j] || !bufs[j + 1] || bufs[j] == bufs[j + 1])
       return fail(LBM_EINVAL, "bufs[%d] and bufs[%d] must be two distinct device buffers", j, j + 1);
   if (int st = set_device(ctx)) return st;
-  using S = StepTile;
-  const int ntx = tiles_x<S>(ctx->p.nx), ntiles = tiles_total<S>(ctx->p.nx, ctx->p.ny);
-  for (int32_t j = 0; j < n; ++j)
-    step_kernel<S, StoreF32><<<ntiles, dim3(S::TX, S::WY), 0, ctx->stream>>>(
-        bufs[j], bufs[j + 1], nullptr, nullptr, ctx->p.nx, ctx->p.ny, ntx, ntiles, strip_width(ntx, false), ctx->c,
-        ctx->q);
+  for (int32_t j = 0; j < n; ++j) launch_step<StoreF32>(ctx, bufs[j], bufs[j + 1], nullptr, nullptr);
   HIP_OK(hipGetLastError());
   return LBM_OK;
 }
@@ -1259,7 +1274,7 @@ int lbm_adjoint_step(lbm_ctx* ctx, const void* f_t, const void* adj_next, void* 
   const int ntx = tiles_x<S>(ctx->p.nx), ntiles = ctx->adj_blocks;
   adjoint_step_kernel<S><<<ntiles, dim3(S::TX, S::WY), 0, ctx->stream>>>(
       static_cast<const float*>(f_t), static_cast<const float*>(adj_next), static_cast<float*>(adj_out),
-      ctx->theta, ctx->p.nx, ctx->p.ny, ntx, ntiles, strip_width(ntx, false), ctx->c);
+      ctx->theta, ctx->p.nx, ctx->p.ny, ntx, ntiles, strip_width(ctx->p.nx, S::TX, false), ctx->c);
   HIP_OK(hipGetLastError());
   return LBM_OK;
 }
@@ -1282,8 +1297,8 @@ int lbm_adjoint_run(lbm_ctx* ctx, const void* const* f_states, int32_t n, void* 
   for (int32_t j = n - 1; j >= 0; --j) {
     adjoint_step_kernel<S><<<ntiles, dim3(S::TX, S::WY), 0, ctx->stream>>>(
         static_cast<const float*>(f_states[j]), static_cast<const float*>(buf[cur]),
-        static_cast<float*>(buf[cur ^ 1]), ctx->theta, ctx->p.nx, ctx->p.ny, ntx, ntiles, strip_width(ntx, false),
-        ctx->c);
+        static_cast<float*>(buf[cur ^ 1]), ctx->theta, ctx->p.nx, ctx->p.ny, ntx, ntiles,
+        strip_width(ctx->p.nx, S::TX, false), ctx->c);
     cur ^= 1;
   }
   HIP_OK(hipGetLastError());
