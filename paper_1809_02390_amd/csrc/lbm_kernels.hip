@@ -612,24 +612,48 @@ using AdjTile = TileShape<LBM_ADJ_TILE>;
 template <class S>
 struct AdjLds {
   static constexpr int AW = S::TX + 4, AH = S::TY + 4, NA = AW * AH;
-  static constexpr int NRED = 3 * S::NTHREADS;  // doubles of the block reduction
+  static constexpr int NRED = 3 * (S::NTHREADS / 64);  // doubles of the block reduction (one per wave)
   // floats of the LDS buffer that holds the A halo, then the reduction
   static constexpr int NSA = 2 * NA > 2 * NRED ? 2 * NA : 2 * NRED;
 };
 
-// A on the tile plus a two-node ring into sa[2][AH][AW], then nu on the tile
-// plus a one-node ring into snu[(TY+2)][LW].  Ends with a barrier.
+// A on the tile plus a two-node ring ((TY+4) x (TX+4) nodes), held in
+// registers by the thread that stages it: halo node p = tid + r * NTHREADS.
+template <class S>
+struct AHalo {
+  static constexpr int R = (AdjLds<S>::NA + S::NTHREADS - 1) / S::NTHREADS;
+  float v[R][2];
+};
+
 template <class S, bool kInterior = false>
-__device__ __forceinline__ void stage_nu(const float* __restrict__ ax, const float* __restrict__ ay, int nx, int ny,
-                                         int x0, int y0, float* sa, float* snu) {
+__device__ __forceinline__ void load_a(const float* __restrict__ ax, const float* __restrict__ ay, int nx, int ny,
+                                       int x0, int y0, AHalo<S>& h) {
   using L = AdjLds<S>;
   const int tid = threadIdx.y * S::TX + threadIdx.x;
-  for (int p = tid; p < L::NA; p += S::NTHREADS) {
+#pragma unroll
+  for (int r = 0; r < AHalo<S>::R; ++r) {
+    const int p = tid + r * S::NTHREADS;
+    if (p >= L::NA) break;
     const int hx = p % L::AW, hy = p / L::AW;
     const size_t o = kInterior ? (size_t)(y0 + hy - 2) * nx + (x0 + hx - 2)
                                : (size_t)wrap(y0 + hy - 2, ny) * nx + wrap(x0 + hx - 2, nx);
-    sa[p] = ax[o];
-    sa[L::NA + p] = ay[o];
+    h.v[r][0] = ax[o];
+    h.v[r][1] = ay[o];
+  }
+}
+
+// The A halo (load_a's registers) into sa[2][AH][AW], a barrier, then nu on
+// the tile plus a one-node ring into snu[(TY+2)][LW], and a barrier.
+template <class S>
+__device__ __forceinline__ void put_nu(const AHalo<S>& h, float* sa, float* snu) {
+  using L = AdjLds<S>;
+  const int tid = threadIdx.y * S::TX + threadIdx.x;
+#pragma unroll
+  for (int r = 0; r < AHalo<S>::R; ++r) {
+    const int p = tid + r * S::NTHREADS;
+    if (p >= L::NA) break;
+    sa[p] = h.v[r][0];
+    sa[L::NA + p] = h.v[r][1];
   }
   __syncthreads();
   const float third = 1.0f / 3.0f, twelfth = 1.0f / 12.0f;
@@ -648,46 +672,86 @@ __device__ __forceinline__ void stage_nu(const float* __restrict__ ax, const flo
   __syncthreads();
 }
 
+// nu of the tile plus a one-node ring from the A planes (load_a, put_nu).
+template <class S, bool kInterior = false>
+__device__ __forceinline__ void stage_nu(const float* __restrict__ ax, const float* __restrict__ ay, int nx, int ny,
+                                         int x0, int y0, float* sa, float* snu) {
+  AHalo<S> h;
+  load_a<S, kInterior>(ax, ay, nx, ny, x0, y0, h);
+  put_nu<S>(h, sa, snu);
+}
+
 // Deterministic FP64 block sum of three per-thread values, added to this
 // block's slot of partials (a block always owns the same slot, so sums over
-// many launches are reproducible bit for bit).
+// many launches are reproducible bit for bit): a fixed shuffle tree inside
+// each wave, then the waves' sums in wave order.
 template <class S>
 __device__ __forceinline__ void block_accumulate(const float* th, double* red, double* __restrict__ partials) {
-  const int tid = threadIdx.y * S::TX + threadIdx.x;
+  constexpr int NW = S::NTHREADS / 64;
+  const int tid = threadIdx.y * S::TX + threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double v[3] = {(double)th[0], (double)th[1], (double)th[2]};
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] += __shfl_down(v[k], off, 64);
   __syncthreads();  // red aliases LDS read above
+  if (lane == 0)
 #pragma unroll
-  for (int k = 0; k < 3; ++k) red[k * S::NTHREADS + tid] = (double)th[k];
+    for (int k = 0; k < 3; ++k) red[k * NW + wave] = v[k];
   __syncthreads();
-  for (int w = S::NTHREADS / 2; w > 0; w >>= 1) {
-    if (tid < w)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) red[k * S::NTHREADS + tid] += red[k * S::NTHREADS + tid + w];
-    __syncthreads();
+  if (tid < 3) {
+    double s = red[tid * NW];
+    for (int w = 1; w < NW; ++w) s += red[tid * NW + w];
+    partials[(size_t)blockIdx.x * 3 + tid] += s;
   }
-  if (tid < 3) partials[(size_t)blockIdx.x * 3 + tid] += red[tid * S::NTHREADS];
 }
 
 // One tile of the adjoint step (kInterior: interior_tile holds, no wrap).
+// Every global load (the forward populations with their ring, the A halo and
+// the adjoint populations of the own nodes) is issued before the first
+// barrier.
 template <class S, bool kInterior>
 __device__ __forceinline__ void adjoint_tile(const float* __restrict__ fsrc, const float* __restrict__ adj_in,
                                              float* __restrict__ adj_out, int nx, int ny, int x0, int y0,
                                              const Coef<float>& c, float* srho, float* snu, float* sa, float* th) {
   const size_t N = (size_t)nx * ny;
+  const Planes<float> P = planes<float>(adj_in, N);
+  const unsigned rb = 4u * (unsigned)nx;
+  const int x = x0 + threadIdx.x;
+  const unsigned o0 = rb * (unsigned)(y0 + threadIdx.y) + 4u * (unsigned)x;
   float f[S::NPT][9];
   float rho[S::NPT];
+  float lb[S::NPT][9];
+  AHalo<S> h;
   {
     TileRegs<S, StoreF32> R;
     issue_tile<S, StoreF32, kInterior>(planes<float>(fsrc, N), nullptr, nx, ny, x0, y0, R);
+    load_a<S, kInterior>(adj_in + 9 * N, adj_in + 10 * N, nx, ny, x0, y0, h);
+    // lam-bar_i(y) = L_i(y + e_i) (+ nu(y + e_i) below)
+#pragma unroll
+    for (int k = 0; k < S::NPT; ++k) {
+      const int y = y0 + threadIdx.y + k * S::WY;
+      if (x >= nx || y >= ny) break;
+      const unsigned o = o0 + (unsigned)(k * S::WY) * rb;
+      if constexpr (kInterior) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) lb[k][i] = ldb<float>(P.p[i] + (ptrdiff_t)kCy[i] * rb + kCx[i] * 4, o);
+      } else {
+        const NodeAddr<4> a = node_addr<4>(x, y, nx, ny);
+        lb[k][0] = ldb<float>(P.p[0], a.r0 + a.c0);
+        lb[k][1] = ldb<float>(P.p[1], a.r0 + a.cp);
+        lb[k][2] = ldb<float>(P.p[2], a.rp + a.c0);
+        lb[k][3] = ldb<float>(P.p[3], a.r0 + a.cm);
+        lb[k][4] = ldb<float>(P.p[4], a.rm + a.c0);
+        lb[k][5] = ldb<float>(P.p[5], a.rp + a.cp);
+        lb[k][6] = ldb<float>(P.p[6], a.rp + a.cm);
+        lb[k][7] = ldb<float>(P.p[7], a.rm + a.cm);
+        lb[k][8] = ldb<float>(P.p[8], a.rm + a.cp);
+      }
+    }
     stage_tile<S, StoreF32>(R, RefPoly<float>{}, f, rho, srho, nullptr);
   }
-  stage_nu<S, kInterior>(adj_in + 9 * N, adj_in + 10 * N, nx, ny, x0, y0, sa, snu);  // barrier covers srho too
-  const Planes<float> P = planes<float>(adj_in, N);
-  const unsigned rb = 4u * (unsigned)nx;
-  Planes<float> Q;  // interior: Q_i + offset(y) = P_i + offset(y + e_i)
-#pragma unroll
-  for (int i = 0; i < 9; ++i) Q.p[i] = P.p[i] + (ptrdiff_t)kCy[i] * rb + kCx[i] * 4;
-  const int x = x0 + threadIdx.x;
-  const unsigned o0 = rb * (unsigned)(y0 + threadIdx.y) + 4u * (unsigned)x;
+  put_nu<S>(h, sa, snu);  // its barriers cover srho too
 #pragma unroll
   for (int k = 0; k < S::NPT; ++k) {
     const int ly = threadIdx.y + k * S::WY, y = y0 + ly;
@@ -697,28 +761,11 @@ __device__ __forceinline__ void adjoint_tile(const float* __restrict__ fsrc, con
     neighbours<S>(srho, hx, hy, nb);
     float gx, gy;
     stencil(nb[1], nb[2], nb[3], nb[4], nb[5], nb[6], nb[7], nb[8], gx, gy);
-    // lam-bar_i(y) = L_i(y + e_i) + nu(y + e_i)
-    const unsigned o = o0 + (unsigned)(k * S::WY) * rb;
-    float lb[9];
-    if constexpr (kInterior) {
 #pragma unroll
-      for (int i = 0; i < 9; ++i) lb[i] = ldb<float>(Q.p[i], o);
-    } else {
-      const NodeAddr<4> a = node_addr<4>(x, y, nx, ny);
-      lb[0] = ldb<float>(P.p[0], a.r0 + a.c0);
-      lb[1] = ldb<float>(P.p[1], a.r0 + a.cp);
-      lb[2] = ldb<float>(P.p[2], a.rp + a.c0);
-      lb[3] = ldb<float>(P.p[3], a.r0 + a.cm);
-      lb[4] = ldb<float>(P.p[4], a.rm + a.c0);
-      lb[5] = ldb<float>(P.p[5], a.rp + a.cp);
-      lb[6] = ldb<float>(P.p[6], a.rp + a.cm);
-      lb[7] = ldb<float>(P.p[7], a.rm + a.cm);
-      lb[8] = ldb<float>(P.p[8], a.rm + a.cp);
-    }
-#pragma unroll
-    for (int i = 0; i < 9; ++i) lb[i] += snu[pos + kCy[i] * S::LW + kCx[i]];
+    for (int i = 0; i < 9; ++i) lb[k][i] += snu[pos + kCy[i] * S::LW + kCx[i]];
     float lf[9], agx = 0.0f, agy = 0.0f;
-    collide_node_vjp<float>(f[k], gx, gy, c, lb, lf, agx, agy, th);
+    collide_node_vjp<float>(f[k], gx, gy, c, lb[k], lf, agx, agy, th);
+    const unsigned o = o0 + (unsigned)(k * S::WY) * rb;
     char* out = reinterpret_cast<char*>(adj_out);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
