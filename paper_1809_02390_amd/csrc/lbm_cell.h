@@ -293,13 +293,15 @@ __host__ __device__ __forceinline__ void transpose_moments(const T* a, T* f) {
 // Reverse-mode derivative of collide_node.  Given the pre-collision
 // populations f, the stencil gradient g and lam = dL/d f-bar, returns
 // lam_f = dL/d f (at fixed g), a_g = dL/d g, and adds dL/d(G'^2, K', R T)
-// to a_th.  The forward quantities are recomputed here; the sweep visits the
-// assignments of collide_node / collide_scaled / node_state / eos in
-// reverse order, written for the unscaled moments (m-bar = m + D^-1 w).
+// to a_th.  f-bar = f + M^T w with w from collide_scaled, so dL/dw = M lam;
+// the sweep visits the assignments of collide_scaled, node_state and eos in
+// reverse order, gathering the cotangents of the cubic velocity monomials
+// (shared by the force moments and the T and X terms) before they are
+// carried to u.
 template <typename T>
 __host__ __device__ __forceinline__ void collide_node_vjp(const T* f, T gx, T gy, const Coef<T>& c, const T* lam,
                                                           T* lam_f, T& a_gx, T& a_gy, T* a_th) {
-  // ---- forward recomputation --------------------------------------------
+  // ---- forward recomputation (collide_node) ------------------------------
   T m[9];
   forward_moments(f, m);
   const T rho = m[0];
@@ -315,145 +317,116 @@ __host__ __device__ __forceinline__ void collide_node_vjp(const T* f, T gx, T gy
   const T dp = c.kprt * dz + c.de_rho * rho;
   const T eta = T(3) * p - rho;
   const T ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy, u2 = ux2 + uy2, dxy = ux2 - uy2;
+  const T c3x = ux * ux2, c3y = uy * uy2, cxyy = uxy * uy, cxxy = uxy * ux;
   const T meq1 = T(2) * (eta - rho) + T(3) * rho * u2;
   const T meq2 = c.alpha2 * rho + c.beta2 * eta + rho * (T(9) * ux2 * uy2 - T(3) * u2);
-  const T meq4 = rho * ux * (T(3) * uy2 - T(1));
-  const T meq6 = rho * uy * (T(3) * ux2 - T(1));
+  const T meq4 = rho * (T(3) * cxyy - ux), meq6 = rho * (T(3) * cxxy - uy);
   const T meq7 = rho * dxy, meq8 = rho * uxy;
-  const T Fu3 = T(3) * (Fx * ux + Fy * uy);
-  const T hF2 = T(9) * (Fx * ux * uy2 + Fy * uy * ux2) - Fu3;
+  const T Fxu = Fx * ux, Fyu = Fy * uy;
+  const T Fu3 = T(3) * (Fxu + Fyu);
+  const T hF2 = T(9) * (Fx * cxyy + Fy * cxxy) - Fu3;
   const T hF4 = T(1.5) * (Fx * uy2 + T(2) * Fy * uxy) - T(0.5) * Fx;
   const T hF6 = T(1.5) * (Fy * ux2 + T(2) * Fx * uxy) - T(0.5) * Fy;
-  const T hF7 = Fx * ux - Fy * uy;
+  const T hF7 = Fxu - Fyu;
   const T hF8 = T(0.5) * (Fx * uy + Fy * ux);
   const T d1 = m[1] - meq1 + Fu3, d2 = m[2] - meq2 + hF2, d4 = m[4] - meq4 + hF4;
   const T d6 = m[6] - meq6 + hF6, d7 = m[7] - meq7 + hF7, d8 = m[8] - meq8 + hF8;
   const T D1 = c.om_e * (d1 + c.k_seps_h * d2 + c.h_sq_h * (ux * d4 + uy * d6));
   const T D7 = c.om_p * (d7 + c.b_sq * (ux * d4 - uy * d6));
   const T D8 = c.om_p * (d8 + c.b_sq_h * (uy * d4 + ux * d6));
-  const T R11 = c.cR11 * u2, R17 = c.cR17 * dxy, R18 = c.cR18 * uxy;
-  const T t1x = ux * (c.cT1a * ux2 - c.cT1b * uy2), t1y = uy * (c.cT1a * uy2 - c.cT1b * ux2);
-  const T x1x = c.cX1 * uxy * uy, x1y = c.cX1 * uxy * ux;
-  const T R71 = c.cR71 * dxy, R77 = c.cR77 * u2;
-  const T t7x = c.cT7 * ux * (ux2 + c.two_b * uy2), t7y = -c.cT7 * uy * (uy2 + c.two_b * ux2);
-  const T x7x = c.cX7 * uxy * uy, x7y = -c.cX7 * uxy * ux;
-  const T R81 = c.cR81 * uxy, R88 = c.cR88 * u2;
-  const T v8x = uy * (uy2 + T(2) * ux2), v8y = ux * (ux2 + T(2) * uy2);
-  const T W8 = c.cT8 + dp * c.cX8, V8 = v8x * gx + v8y * gy;
   const T gg = gx * gx + gy * gy;
+  const T b1 = dp * c.w_x1 + c.w_t1b, b7 = dp * c.w_x7 + c.w_t7b, b8 = dp * c.w_x8 + c.w_t8;
+  const T v8x = c3y + T(2) * cxxy, v8y = c3x + T(2) * cxyy;
 
-  // ---- lam of the post-collision moments: (M^-1)^T lam = D M lam ---------
-  T l[9];
-  forward_moments(lam, l);
-  l[0] *= T(1.0 / 9.0), l[1] *= T(1.0 / 36.0), l[2] *= T(1.0 / 36.0), l[3] *= T(1.0 / 6.0);
-  l[4] *= T(1.0 / 12.0), l[5] *= T(1.0 / 6.0), l[6] *= T(1.0 / 12.0), l[7] *= T(0.25), l[8] *= T(0.25);
-
-  T a_rho = l[0], a_ux = 0, a_uy = 0, a_Fx = l[3], a_Fy = l[5], a_dp = 0, a_eta = 0, a_g2 = 0;
-  T a_m[9] = {0, 0, 0, l[3], 0, l[5], 0, 0, 0};
-  a_gx = 0, a_gy = 0;
-  // post-collision rows (collide_scaled steps (5)-(6))
-  T a_meq1 = l[1], a_hF1 = l[1], a_d1 = -l[1], a_D1 = T(2) * l[1], a_c1 = -l[1];
-  T a_gg = c.q1 * l[1] - c.s_eps * T(0.5) * c.g2 * l[2];
-  a_g2 += T(0.5) * (c.s_e - c.kq2) * gg * l[1] - c.s_eps * T(0.5) * gg * l[2];
-  T a_meq2 = l[2], a_hF2 = l[2], a_d2 = c.one_m_seps * l[2];
-  T a_meq4 = l[4], a_hF4 = l[4], a_d4 = c.one_m_sq * l[4];
-  T a_meq6 = l[6], a_hF6 = l[6], a_d6 = c.one_m_sq * l[6];
-  T a_meq7 = l[7], a_hF7 = l[7], a_d7 = -l[7], a_D7 = T(2) * l[7], a_c7 = -l[7];
-  a_gx += T(2) * c.q7 * gx * l[7], a_gy -= T(2) * c.q7 * gy * l[7];
-  a_g2 += c.s_p * T(1.0 / 12.0) * (gx * gx - gy * gy) * l[7];
-  T a_meq8 = l[8], a_hF8 = l[8], a_d8 = -l[8], a_D8 = T(2) * l[8], a_c8 = -l[8];
-  a_gx += c.q7 * gy * l[8], a_gy += c.q7 * gx * l[8];
-  a_g2 += c.s_p * T(1.0 / 12.0) * gx * gy * l[8];
+  // ---- w: dL/dw = M lam ------------------------------------------------------
+  T W[9];
+  forward_moments(lam, W);
+  const T A1 = W[1], A7 = W[7], A8 = W[8];
+  T a_Fx = W[3] * T(1.0 / 6.0), a_Fy = W[5] * T(1.0 / 6.0);
+  // w1
+  T a_D1 = (T(2.0 / 36.0) + c.w_r11 * u2) * A1, a_d1 = -T(2.0 / 36.0) * A1, a_Fu3 = T(2.0 / 36.0) * A1;
+  T a_u2 = c.w_r11 * D1 * A1, a_dxy = c.w_r17 * D7 * A1, a_uxy = c.w_r18 * D8 * A1;
+  T a_D7 = c.w_r17 * dxy * A1, a_D8 = c.w_r18 * uxy * A1;
+  const T gx1 = gx * A1, gy1 = gy * A1;
+  T a_c3x = c.w_t1a * gx1, a_c3y = c.w_t1a * gy1, a_cxyy = b1 * gx1, a_cxxy = b1 * gy1;
+  T a_dp = c.w_x1 * (cxyy * gx1 + cxxy * gy1);
+  a_gx = (c.w_t1a * c3x + b1 * cxyy) * A1;
+  a_gy = (c.w_t1a * c3y + b1 * cxxy) * A1;
+  T a_gg = c.w_q1 * A1 - c.w_q2 * W[2];
+  // w2, w4, w6
+  T a_hF2 = T(2.0 / 36.0) * W[2], a_d2 = -c.w_seps * W[2];
+  T a_hF4 = T(1.0 / 6.0) * W[4], a_d4 = -c.w_sq * W[4];
+  T a_hF6 = T(1.0 / 6.0) * W[6], a_d6 = -c.w_sq * W[6];
+  // w7
+  a_D7 += (T(0.5) + c.w_r77 * u2) * A7;
+  T a_d7 = -T(0.5) * A7, a_hF7 = T(0.5) * A7;
+  a_dxy += c.w_r71 * D1 * A7, a_D1 += c.w_r71 * dxy * A7, a_u2 += c.w_r77 * D7 * A7;
+  const T gx7 = gx * A7, gy7 = gy * A7;
+  a_c3x += c.w_t7 * gx7, a_c3y -= c.w_t7 * gy7, a_cxyy += b7 * gx7, a_cxxy -= b7 * gy7;
+  a_dp += c.w_x7 * (cxyy * gx7 - cxxy * gy7);
+  a_gx += (c.w_t7 * c3x + b7 * cxyy) * A7 + T(2) * c.w_q7 * gx7;
+  a_gy -= (c.w_t7 * c3y + b7 * cxxy) * A7 + T(2) * c.w_q7 * gy7;
+  // w8
+  a_D8 += (T(0.5) + c.w_r88 * u2) * A8;
+  T a_d8 = -T(0.5) * A8, a_hF8 = T(0.5) * A8;
+  a_uxy += c.w_r81 * D1 * A8, a_D1 += c.w_r81 * uxy * A8, a_u2 += c.w_r88 * D8 * A8;
+  const T b8A = b8 * A8, gxb = gx * b8A, gyb = gy * b8A;
+  a_c3y += gxb, a_cxxy += T(2) * gxb, a_c3x += gyb, a_cxyy += T(2) * gyb;
+  a_dp += c.w_x8 * (v8x * gx + v8y * gy) * A8;
+  a_gx += v8x * b8A + c.w_q7 * gy * A8;
+  a_gy += v8y * b8A + c.w_q7 * gx * A8;
   a_gx += T(2) * gx * a_gg, a_gy += T(2) * gy * a_gg;
-
-  T a_u2 = 0, a_dxy = 0, a_uxy = 0, a_ux2 = 0, a_uy2 = 0;
-  // corr8 = R81 D1 + R88 D8 + W8 V8
+  // G'^2 through the Q_m terms: w_q1, w_q2, w_q7 are G'^2 (s_e - kq2)/72,
+  // G'^2 s_eps/72 and G'^2 s_p/48
+  T a_g2 = T(1.0 / 72.0) * gg * ((c.s_e - c.kq2) * A1 - c.s_eps * W[2]) +
+           c.s_p * T(1.0 / 48.0) * ((gx * gx - gy * gy) * A7 + gx * gy * A8);
+  // D1 = om_e (d1 + k_seps_h d2 + h_sq_h (ux d4 + uy d6))
+  T a_ux, a_uy;
   {
-    a_uxy += c.cR81 * D1 * a_c8, a_D1 += R81 * a_c8;
-    a_u2 += c.cR88 * D8 * a_c8, a_D8 += R88 * a_c8;
-    a_dp += c.cX8 * V8 * a_c8;
-    const T a_V = W8 * a_c8;
-    const T a_v8x = gx * a_V, a_v8y = gy * a_V;
-    a_gx += v8x * a_V, a_gy += v8y * a_V;
-    a_ux += T(4) * uxy * a_v8x + (T(3) * ux2 + T(2) * uy2) * a_v8y;
-    a_uy += (T(3) * uy2 + T(2) * ux2) * a_v8x + T(4) * uxy * a_v8y;
-  }
-  // corr7 = R71 D1 + R77 D7 + (t7x + dp x7x) gx + (t7y + dp x7y) gy
-  {
-    a_dxy += c.cR71 * D1 * a_c7, a_D1 += R71 * a_c7;
-    a_u2 += c.cR77 * D7 * a_c7, a_D7 += R77 * a_c7;
-    a_dp += (x7x * gx + x7y * gy) * a_c7;
-    a_gx += (t7x + dp * x7x) * a_c7, a_gy += (t7y + dp * x7y) * a_c7;
-    const T a_t7x = gx * a_c7, a_t7y = gy * a_c7, a_x7x = dp * gx * a_c7, a_x7y = dp * gy * a_c7;
-    a_ux += c.cT7 * (T(3) * ux2 + c.two_b * uy2) * a_t7x - c.cT7 * T(2) * c.two_b * uxy * a_t7y;
-    a_uy += c.cT7 * T(2) * c.two_b * uxy * a_t7x - c.cT7 * (T(3) * uy2 + c.two_b * ux2) * a_t7y;
-    a_ux += c.cX7 * uy2 * a_x7x - T(2) * c.cX7 * uxy * a_x7y;
-    a_uy += T(2) * c.cX7 * uxy * a_x7x - c.cX7 * ux2 * a_x7y;
-  }
-  // corr1 = R11 D1 + R17 D7 + R18 D8 + (t1x + dp x1x) gx + (t1y + dp x1y) gy
-  {
-    a_u2 += c.cR11 * D1 * a_c1, a_D1 += R11 * a_c1;
-    a_dxy += c.cR17 * D7 * a_c1, a_D7 += R17 * a_c1;
-    a_uxy += c.cR18 * D8 * a_c1, a_D8 += R18 * a_c1;
-    a_dp += (x1x * gx + x1y * gy) * a_c1;
-    a_gx += (t1x + dp * x1x) * a_c1, a_gy += (t1y + dp * x1y) * a_c1;
-    const T a_t1x = gx * a_c1, a_t1y = gy * a_c1, a_x1x = dp * gx * a_c1, a_x1y = dp * gy * a_c1;
-    a_ux += (T(3) * c.cT1a * ux2 - c.cT1b * uy2) * a_t1x - T(2) * c.cT1b * uxy * a_t1y;
-    a_uy += -T(2) * c.cT1b * uxy * a_t1x + (T(3) * c.cT1a * uy2 - c.cT1b * ux2) * a_t1y;
-    a_ux += c.cX1 * uy2 * a_x1x + T(2) * c.cX1 * uxy * a_x1y;
-    a_uy += T(2) * c.cX1 * uxy * a_x1x + c.cX1 * ux2 * a_x1y;
-  }
-  // D8 = om_p (d8 + b_sq_h (uy d4 + ux d6))
-  {
-    a_d8 += c.om_p * a_D8;
-    const T t = c.om_p * c.b_sq_h * a_D8;
-    a_uy += d4 * t, a_d4 += uy * t, a_ux += d6 * t, a_d6 += ux * t;
+    const T t = c.om_e * a_D1, th = c.h_sq_h * t;
+    a_d1 += t, a_d2 += c.k_seps_h * t;
+    a_ux = d4 * th, a_uy = d6 * th, a_d4 += ux * th, a_d6 += uy * th;
   }
   // D7 = om_p (d7 + b_sq (ux d4 - uy d6))
   {
-    a_d7 += c.om_p * a_D7;
-    const T t = c.om_p * c.b_sq * a_D7;
-    a_ux += d4 * t, a_d4 += ux * t, a_uy -= d6 * t, a_d6 -= uy * t;
+    const T t = c.om_p * a_D7, tb = c.b_sq * t;
+    a_d7 += t;
+    a_ux += d4 * tb, a_d4 += ux * tb, a_uy -= d6 * tb, a_d6 -= uy * tb;
   }
-  // D1 = om_e (d1 + k_seps_h d2 + h_sq_h (ux d4 + uy d6))
+  // D8 = om_p (d8 + b_sq_h (uy d4 + ux d6))
   {
-    a_d1 += c.om_e * a_D1;
-    a_d2 += c.om_e * c.k_seps_h * a_D1;
-    const T t = c.om_e * c.h_sq_h * a_D1;
-    a_ux += d4 * t, a_d4 += ux * t, a_uy += d6 * t, a_d6 += uy * t;
+    const T t = c.om_p * a_D8, tb = c.b_sq_h * t;
+    a_d8 += t;
+    a_uy += d4 * tb, a_d4 += uy * tb, a_ux += d6 * tb, a_d6 += ux * tb;
   }
-  // d_k = m_k - meq_k + hF_k
-  a_m[1] += a_d1, a_meq1 -= a_d1, a_hF1 += a_d1;
-  a_m[2] += a_d2, a_meq2 -= a_d2, a_hF2 += a_d2;
-  a_m[4] += a_d4, a_meq4 -= a_d4, a_hF4 += a_d4;
-  a_m[6] += a_d6, a_meq6 -= a_d6, a_hF6 += a_d6;
-  a_m[7] += a_d7, a_meq7 -= a_d7, a_hF7 += a_d7;
-  a_m[8] += a_d8, a_meq8 -= a_d8, a_hF8 += a_d8;
+  // d_k = m_k - meq_k + hF_k (hF_1 = Fu3)
+  a_Fu3 += a_d1, a_hF2 += a_d2, a_hF4 += a_d4, a_hF6 += a_d6, a_hF7 += a_d7, a_hF8 += a_d8;
   // half force moments
+  a_Fu3 -= a_hF2;
+  a_Fx += T(9) * cxyy * a_hF2, a_cxyy += T(9) * Fx * a_hF2;
+  a_Fy += T(9) * cxxy * a_hF2, a_cxxy += T(9) * Fy * a_hF2;
+  a_Fx += (T(1.5) * uy2 - T(0.5)) * a_hF4, a_Fy += T(3) * uxy * a_hF4, a_uxy += T(3) * Fy * a_hF4;
+  T a_uy2 = T(1.5) * Fx * a_hF4;
+  a_Fy += (T(1.5) * ux2 - T(0.5)) * a_hF6, a_Fx += T(3) * uxy * a_hF6, a_uxy += T(3) * Fx * a_hF6;
+  T a_ux2 = T(1.5) * Fy * a_hF6;
   a_Fx += T(0.5) * uy * a_hF8, a_uy += T(0.5) * Fx * a_hF8, a_Fy += T(0.5) * ux * a_hF8, a_ux += T(0.5) * Fy * a_hF8;
-  a_Fx += ux * a_hF7, a_ux += Fx * a_hF7, a_Fy -= uy * a_hF7, a_uy -= Fy * a_hF7;
-  a_Fy += (T(1.5) * ux2 - T(0.5)) * a_hF6, a_ux2 += T(1.5) * Fy * a_hF6, a_Fx += T(3) * uxy * a_hF6,
-      a_uxy += T(3) * Fx * a_hF6;
-  a_Fx += (T(1.5) * uy2 - T(0.5)) * a_hF4, a_uy2 += T(1.5) * Fx * a_hF4, a_Fy += T(3) * uxy * a_hF4,
-      a_uxy += T(3) * Fy * a_hF4;
-  T a_Fu3 = a_hF1 - a_hF2;
-  a_Fx += T(9) * ux * uy2 * a_hF2, a_ux += T(9) * Fx * uy2 * a_hF2, a_uy2 += T(9) * Fx * ux * a_hF2;
-  a_Fy += T(9) * uy * ux2 * a_hF2, a_uy += T(9) * Fy * ux2 * a_hF2, a_ux2 += T(9) * Fy * uy * a_hF2;
-  a_Fx += T(3) * ux * a_Fu3, a_ux += T(3) * Fx * a_Fu3, a_Fy += T(3) * uy * a_Fu3, a_uy += T(3) * Fy * a_Fu3;
-  // equilibrium moments
-  a_rho += uxy * a_meq8, a_uxy += rho * a_meq8;
-  a_rho += dxy * a_meq7, a_dxy += rho * a_meq7;
-  a_rho += uy * (T(3) * ux2 - T(1)) * a_meq6, a_uy += rho * (T(3) * ux2 - T(1)) * a_meq6,
-      a_ux2 += T(3) * rho * uy * a_meq6;
-  a_rho += ux * (T(3) * uy2 - T(1)) * a_meq4, a_ux += rho * (T(3) * uy2 - T(1)) * a_meq4,
-      a_uy2 += T(3) * rho * ux * a_meq4;
-  a_rho += (c.alpha2 + T(9) * ux2 * uy2 - T(3) * u2) * a_meq2, a_eta += c.beta2 * a_meq2;
-  a_ux2 += T(9) * rho * uy2 * a_meq2, a_uy2 += T(9) * rho * ux2 * a_meq2, a_u2 -= T(3) * rho * a_meq2;
-  a_eta += T(2) * a_meq1, a_rho += (T(3) * u2 - T(2)) * a_meq1, a_u2 += T(3) * rho * a_meq1;
-  // velocity products
-  a_ux2 += a_u2 + a_dxy, a_uy2 += a_u2 - a_dxy;
-  a_ux += uy * a_uxy + T(2) * ux * a_ux2;
-  a_uy += ux * a_uxy + T(2) * uy * a_uy2;
+  const T a_Fxu = T(3) * a_Fu3 + a_hF7, a_Fyu = T(3) * a_Fu3 - a_hF7;
+  a_Fx += ux * a_Fxu, a_ux += Fx * a_Fxu, a_Fy += uy * a_Fyu, a_uy += Fy * a_Fyu;
+  // equilibrium moments (dL/d meq_k = -dL/d d_k)
+  T a_eta = -(T(2) * a_d1 + c.beta2 * a_d2);
+  T a_rho = -((T(3) * u2 - T(2)) * a_d1 + (c.alpha2 + T(9) * ux2 * uy2 - T(3) * u2) * a_d2 +
+              (T(3) * cxyy - ux) * a_d4 + (T(3) * cxxy - uy) * a_d6 + dxy * a_d7 + uxy * a_d8);
+  a_u2 -= T(3) * rho * (a_d1 - a_d2);
+  const T r9 = -T(9) * rho * a_d2;
+  a_ux2 += uy2 * r9, a_uy2 += ux2 * r9;
+  a_cxyy -= T(3) * rho * a_d4, a_ux += rho * a_d4;
+  a_cxxy -= T(3) * rho * a_d6, a_uy += rho * a_d6;
+  a_dxy -= rho * a_d7, a_uxy -= rho * a_d8;
+  // velocity monomials
+  a_ux2 += a_u2 + a_dxy + ux * a_c3x, a_uy2 += a_u2 - a_dxy + uy * a_c3y;
+  a_uxy += uy * a_cxyy + ux * a_cxxy;
+  a_ux += ux2 * a_c3x + uxy * a_cxxy + uy * a_uxy + T(2) * ux * a_ux2;
+  a_uy += uy2 * a_c3y + uxy * a_cxyy + ux * a_uxy + T(2) * uy * a_uy2;
   // ---- node state ----------------------------------------------------------
   // eta = 3 p - rho;  dp = kprt dz + de_rho rho;  p = rho (kprt z + e_rho rho)
   const T a_p = T(3) * a_eta;
@@ -467,20 +440,23 @@ __host__ __device__ __forceinline__ void collide_node_vjp(const T* f, T gx, T gy
   // d dz / d rho = (b/4) (8 + 20 v - 4 v^2) / (1 - v)^5
   a_rho += a_z * (dz - z) * inv + a_dz * c.b4 * (T(8) + v * (T(20) - T(4) * v)) * (iw3 * iw * iw);
   // u = (j + F/2) / rho
-  a_m[3] += inv * a_ux, a_Fx += T(0.5) * inv * a_ux;
-  a_m[5] += inv * a_uy, a_Fy += T(0.5) * inv * a_uy;
-  a_rho -= (ux * a_ux + uy * a_uy) * inv;
+  const T a_m3 = inv * a_ux, a_m5 = inv * a_uy;
+  a_Fx += T(0.5) * a_m3, a_Fy += T(0.5) * a_m5;
+  a_rho -= ux * a_m3 + uy * a_m5;
   // F = G'^2 rho g
-  a_rho += c.g2 * (gx * a_Fx + gy * a_Fy);
+  const T gF = gx * a_Fx + gy * a_Fy;
+  a_rho += c.g2 * gF;
   a_gx += c.g2 * rho * a_Fx, a_gy += c.g2 * rho * a_Fy;
-  a_g2 += rho * (gx * a_Fx + gy * a_Fy);
+  a_g2 += rho * gF;
   // parameters: kprt = K' RT, e_rho = G'^2/2 - K' a, de_rho = G'^2 - 2 K' a
   a_th[0] += a_g2 + T(0.5) * a_erho + a_derho;
   a_th[1] += c.rt * a_kprt - c.a * a_erho - T(2) * c.a * a_derho;
   a_th[2] += c.kp * a_kprt;
-  // ---- populations: m = M f and rho = sum f ------------------------------
-  a_m[0] = a_rho;
-  transpose_moments(a_m, lam_f);
+  // ---- populations: lam_f = lam + M^T dL/dm ---------------------------------
+  const T am[9] = {a_rho, a_d1, a_d2, a_m3, a_d4, a_m5, a_d6, a_d7, a_d8};
+  transpose_moments(am, lam_f);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) lam_f[i] += lam[i];
 }
 
 // Adjoint of the equilibrium initial state f^eq(rho0, u0, eta(rho0)) with
