@@ -605,7 +605,7 @@ __global__ __launch_bounds__(BLK) void get_state_kernel(const void* __restrict__
 //                            (rho and g recomputed as the forward step has them)
 // ---------------------------------------------------------------------------
 #ifndef LBM_ADJ_TILE
-#define LBM_ADJ_TILE 128, 4, 4
+#define LBM_ADJ_TILE 64, 8, 4
 #endif
 using AdjTile = TileShape<LBM_ADJ_TILE>;
 
