@@ -53,9 +53,12 @@ def param_term_scale(f, lam, co):
     return np.array(out)
 
 
-@pytest.fixture(scope="module")
-def case():
-    nx, ny = 40, 30
+@pytest.fixture(scope="module", params=[(40, 30), (200, 35)], ids=["40x30", "200x35"])
+def case(request):
+    """A small lattice (every tile touches the periodic edge), and one with
+    interior adjoint tiles next to ragged edges in both directions.  Sides
+    are multiples of 5 for the oracle's colouring."""
+    nx, ny = request.param
     _, co = params_pair(nx, ny, tr=0.7, width=5.0)
     f = nonequilibrium_state(nx, ny, co, 5)
     lam = f32(np.random.default_rng(6).standard_normal(f.shape))
