@@ -24,6 +24,8 @@ Prints one JSON line:
   legs.coalescence_16384x8192  the step on the largest workload, each storage;
   legs.elliptic_droplet  oscillation period of the paper's elliptic droplet
                      against the linear capillary mode;
+  legs.head_on_collision  liquid bodies over time in head-on collisions of
+                     two droplets at the paper's four (We, Re) pairs;
   cpu_baseline       the FP64 oracle timed on a bounded crop.
 """
 from __future__ import annotations
@@ -151,6 +153,47 @@ def ellipse_leg(pkg, wl, n=512, tr=0.6, width=10.0, s_p=1.4, every=100, nsamp=60
     return {"workload": f"elliptic droplet 96.0 x 42.7 on {n}^2, T/Tc={tr}, W={width}, s_p={s_p}",
             "period_steps": round(period, 1), "analytic_steps": round(float(analytic), 1),
             "rel_err": round(period / analytic - 1, 5)}
+
+
+# Head-on collision regimes: We, Re, the dimensionless end time t* = t U / D,
+# and the outcome the paper describes.
+HEAD_ON = {"a": (0.01, 1.0, 2.5, "merge"), "b": (0.1, 1.0, 6.0, "bounce"),
+           "c": (20.0, 100.0, 12.0, "merge, large deformation"),
+           "d": (60.0, 200.0, 20.0, "two droplets and a central satellite")}
+
+
+def head_on_leg(pkg, wl, n=1024, diameter=128.0, gap=60.0, tr=0.7, width=10.0, nsamp=12):
+    """Head-on collision of equal droplets (1024^2, D = 128, T_r = 0.7,
+    W = 10) at the four (We, Re) pairs of the paper: the number of liquid
+    bodies (rho above the mean of the coexistence densities, 4-connected)
+    at nsamp times up to t*.  U from We = rho_l U^2 D / sigma, s_p from
+    Re = U D / nu; the droplet surfaces start `gap` nodes apart."""
+    from scipy import ndimage
+    d = pkg.lbm_derive(pkg.make_params(n, n, tr=tr, width=width))
+    level = 0.5 * (d.rho_l + d.rho_g)
+    out = {"workload": f"head-on collision, {n}x{n}, D={diameter:g}, gap={gap:g}, T/Tc={tr}, W={width}"}
+    for case, (We, Re, t_end, paper) in HEAD_ON.items():
+        U = float(np.sqrt(We * d.sigma / (d.rho_l * diameter)))
+        s_p = 1.0 / (3.0 * U * diameter / Re + 0.5)
+        rho0, ux0, uy0 = wl.head_on(d, U, n=n, diameter=diameter, gap=gap)
+        lat = pkg.Lattice(n, n, tr=tr, width=width, s_p=s_p).init(rho0, ux0, uy0)
+        every = int(round(t_end * diameter / U / nsamp))
+        bodies = []
+        t0 = time.perf_counter()
+        try:
+            for _ in range(nsamp):
+                lat.step(every)
+                lab, count = ndimage.label(lat.moments()[0].cpu().numpy() > level)
+                sizes = ndimage.sum(np.ones(lab.shape), lab, range(1, count + 1))
+                bodies.append(int(np.sum(np.asarray(sizes) > 20)))
+            status = "finite"
+        except pkg.LbmError as e:
+            status = f"diverged ({e})"
+        lat.close()
+        out[case] = {"We": We, "Re": Re, "U": round(U, 6), "s_p": round(s_p, 4), "t_star": t_end,
+                     "steps": every * nsamp, "bodies": bodies, "status": status, "paper": paper,
+                     "s": round(time.perf_counter() - t0, 1)}
+    return out
 
 
 def coexistence_leg(pkg, wl, storage, tr=0.7, width=10.0, ny=128, steps=20000):
@@ -316,6 +359,7 @@ def main():
         legs["fp32_coexistence"] = coexistence_leg(pkg, wl, "fp32")
         legs["coalescence_16384x8192"] = {st: coalescence_leg(pkg, wl, timer, st) for st in ("fp32", "fp16", "bf16")}
         legs["elliptic_droplet"] = ellipse_leg(pkg, wl)
+        legs["head_on_collision"] = head_on_leg(pkg, wl)
         legs["fwd_adjoint"] = fwd_adjoint_leg(pkg, wl, timer, torch)
         legs["fwd_adjoint_keep_all_states"] = fwd_adjoint_leg(pkg, wl, timer, torch, every=1)
         legs["fwd_adjoint"]["adjoint_kernel"] = adjoint_kernel_leg(pkg, wl, timer, torch)

@@ -11,7 +11,7 @@ values.
 Profiles mirror the paper's own test problems: a flat interface (main text,
 coexistence curve), a static droplet (Laplace law), spinodal decomposition of
 a uniform state with noise, droplet pairs and an elliptic droplet (dynamic
-tests).
+tests), and a head-on collision of two moving droplets.
 """
 from __future__ import annotations
 
@@ -114,3 +114,17 @@ def coalescence(derived, nx=16384, ny=8192, radius=400.0, gap=20.0):
     return droplets(nx, ny, _get(derived, "rho_g"), _get(derived, "rho_l"),
                     _get(derived, "width"),
                     [(nx / 2 - d, ny / 2), (nx / 2 + d, ny / 2)], [radius, radius])
+
+
+def head_on(derived, speed, n=1024, diameter=128.0, gap=60.0):
+    """Two equal droplets on the x axis of an n x n lattice, their surfaces
+    ``gap`` apart, approaching each other at relative speed ``speed`` (head-on
+    collision).  Each droplet moves at speed/2 towards the other, weighted by
+    its own liquid fraction; the gas starts at rest.  Returns (rho, ux, uy)."""
+    rg, rl, w = _get(derived, "rho_g"), _get(derived, "rho_l"), _get(derived, "width")
+    d = diameter / 2 + gap / 2
+    centres = [(n / 2 - d, n / 2), (n / 2 + d, n / 2)]
+    rho = droplets(n, n, rg, rl, w, centres, [diameter / 2] * 2)
+    left, right = (droplets(n, n, 0.0, 1.0, w, [c], [diameter / 2]) for c in centres)
+    ux = _f32(0.5 * speed * (left - right))
+    return rho, ux, np.zeros_like(ux)
