@@ -61,12 +61,18 @@ def test_step_parity_within_storage_precision(storage):
 
 
 @pytest.mark.parametrize("storage", STORAGES)
-def test_ragged_lattice_runs_and_matches_fp32(storage):
-    """Ragged tiles: the 2-byte run stays within storage precision of FP32."""
-    _, co = params_pair(70, 37, tr=0.8)
-    rho = wl.droplets(70, 37, co.rho_g, co.rho_l, co.width, [(30, 20)], [11.0])
-    a = lattice(70, 37, rho, tr=0.8, storage=storage)
-    b = lattice(70, 37, rho, tr=0.8)
+@pytest.mark.parametrize("nx,ny", [(70, 37), (400, 37)])
+def test_ragged_lattice_runs_and_matches_fp32(storage, nx, ny):
+    """Ragged tiles: the 2-byte run stays within storage precision of FP32;
+    400 x 37 also has interior tiles (the fast addressing path) next to
+    edge tiles."""
+    _, co = params_pair(nx, ny, tr=0.8)
+    centres, radii = [(30, 20)], [11.0]
+    if nx > 200:  # a second droplet inside the interior tiles
+        centres, radii = centres + [(nx - 150, 17)], radii + [12.0]
+    rho = wl.droplets(nx, ny, co.rho_g, co.rho_l, co.width, centres, radii)
+    a = lattice(nx, ny, rho, tr=0.8, storage=storage)
+    b = lattice(nx, ny, rho, tr=0.8)
     a.step(50)
     b.step(50)
     err = (a.moments()[0] - b.moments()[0]).abs().max().item() / co.rho_l
