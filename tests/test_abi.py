@@ -77,6 +77,13 @@ def test_buffer_sizes():
     assert pkg.lbm_ref_bytes(p16) == 2 * 100 * 30 * 2
 
 
+def test_largest_lattice_accepted():
+    """9 nx ny < 2^31 is the size limit: 16384 x 14563 (9 nx ny = 2147401728)
+    is accepted, one row more is not."""
+    assert pkg.lbm_state_bytes(pkg.make_params(16384, 14563)) == 9 * 16384 * 14563 * 4
+    assert pkg.lbm_state_bytes(pkg.make_params(16384, 14564)) == 0
+
+
 def test_null_context_rejected():
     assert L._lib.lbm_step(None, 1) == L.LBM_EINVAL
     assert L._lib.lbm_time(None) == -1

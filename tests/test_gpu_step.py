@@ -248,6 +248,26 @@ def test_sampled_parity_coalescence_16384x8192():
     assert np.abs(got - ref).max() / co.rho_l <= TOL
 
 
+def test_sampled_parity_largest_lattice():
+    """The largest lattice the library accepts, 16384 x 14563 (9 nx ny just
+    below 2^31; byte offsets inside a plane up to 0.95 GB): the spinodal
+    field (T_r = 0.7, mean of the coexistence densities +- 0.01, seed 3),
+    5 steps, sampled nodes against oracle light-cone crops, including the
+    last row and column."""
+    nx, ny, steps = 16384, 14563, 5
+    _, co = params_pair(nx, ny, tr=0.7, width=10.0)
+    rho = wl.uniform_noise(nx, ny, 0.5 * (co.rho_g + co.rho_l), 0.01, seed=3)
+    lat = lattice(nx, ny, rho, tr=0.7, width=10.0)
+    lat.step(steps)
+    pts = [(nx // 2, ny // 2), (0, 0), (nx - 1, ny - 1), (0, ny - 1), (nx - 1, 0), (12345, ny - 2), (nx - 3, 9999)]
+    ref = sampled_oracle(co, rho, pts, steps)
+    st = lat.state()
+    got = device_samples(st, pts)
+    del st
+    lat.close()
+    assert np.abs(got - ref).max() / co.rho_l <= TOL
+
+
 def test_laplace_law_256():
     """Static droplets R = 20..60 on 256^2 (T_r = 0.8, W = 10, sigma_paper),
     relaxed for 80000 steps (the breathing mode has decayed by 60000): the
