@@ -14,4 +14,4 @@ from .lbm import (  # noqa: F401
     lbm_set_stream, lbm_sigma_paper, lbm_state_bytes, lbm_step, lbm_step_saved, lbm_step_saved_chain, lbm_time,
     make_params,
 )
-from .rollout import LBMRollout, Rollout, lbm_rollout  # noqa: F401
+from .rollout import LBMRollout, Rollout, choose_every, lbm_rollout  # noqa: F401

@@ -23,25 +23,61 @@ Device memory: ceil(n / every) + 1 checkpoints + (every - 1) segment states
 every = 1 every state is kept and nothing is recomputed (the forward +
 adjoint then moves 72 + 124 instead of 72 + 72 + 124 bytes per node and
 step; at 2048^2 x 1000 steps that is 151 GB of checkpoints, which HBM3E
-holds).  Every step of the path runs in the HIP library; this module only
-orders the calls.
+holds).  Any every > 1 recomputes n - ceil(n / every) forward steps, about
+the whole forward pass, so ``every="auto"`` keeps every state when they fit
+in free device memory and otherwise takes every = ceil(sqrt(n)), the
+interval that keeps the fewest states.  Every step of the path runs in the
+HIP library; this module only orders the calls.
 """
 from __future__ import annotations
 
+import math
+
 import torch
 
-from .lbm import Lattice, lbm_adjoint_theta, lbm_param_jacobian
+from .lbm import Lattice, lbm_adjoint_bytes, lbm_adjoint_theta, lbm_checkpoint_bytes, lbm_param_jacobian
+
+
+def rollout_bytes(nsteps, every, state_bytes, adjoint_bytes):
+    """Device bytes a Rollout holds besides the lattice's own buffers:
+    checkpoints, segment states and the two adjoint states."""
+    ckpt = -(-nsteps // every) + 1
+    pool = max(every - 1, 2) if every > 1 else 0
+    return (ckpt + pool) * state_bytes + 2 * adjoint_bytes
+
+
+def choose_every(nsteps, state_bytes, adjoint_bytes, free_bytes, margin=0.8):
+    """Checkpoint interval: 1 if every state fits in margin * free_bytes,
+    else ceil(sqrt(nsteps)); ValueError if not even that fits."""
+    if rollout_bytes(nsteps, 1, state_bytes, adjoint_bytes) <= margin * free_bytes:
+        return 1
+    every = max(2, math.ceil(math.sqrt(max(nsteps, 1))))
+    need = rollout_bytes(nsteps, every, state_bytes, adjoint_bytes)
+    if need > margin * free_bytes:
+        raise ValueError(f"a rollout of {nsteps} steps needs {need / 2**30:.1f} GiB of device memory at "
+                         f"every = {every}; {free_bytes / 2**30:.1f} GiB are free")
+    return every
+
+
+def free_device_bytes(device):
+    """Free device memory, counting what torch's caching allocator holds unused."""
+    dev = torch.device(device)
+    free, _ = torch.cuda.mem_get_info(dev)
+    return free + torch.cuda.memory_reserved(dev) - torch.cuda.memory_allocated(dev)
 
 
 class Rollout:
     """Forward rollout with checkpoints, then one adjoint sweep."""
 
-    def __init__(self, nx, ny, nsteps, every=100, device="cuda", **kw):
+    def __init__(self, nx, ny, nsteps, every="auto", device="cuda", **kw):
         if kw.get("storage", "fp32") not in ("fp32", 0):
             raise ValueError("the adjoint is defined for FP32 storage only")
-        if nsteps < 0 or every < 1:
-            raise ValueError("nsteps >= 0 and every >= 1 are required")
+        if nsteps < 0 or (every != "auto" and int(every) < 1):
+            raise ValueError("nsteps >= 0 and every >= 1 (or 'auto') are required")
         self.lat = Lattice(nx, ny, device=device, **kw)
+        if every == "auto":
+            every = choose_every(int(nsteps), lbm_checkpoint_bytes(self.lat.params),
+                                 lbm_adjoint_bytes(self.lat.params), free_device_bytes(self.lat.f_a.device))
         self.nx, self.ny, self.nsteps, self.every = nx, ny, int(nsteps), int(every)
         self.starts = list(range(0, self.nsteps, self.every))
         self.ckpt = [None] * (len(self.starts) + 1)  # states at the starts, then the final state
@@ -119,6 +155,8 @@ class Rollout:
 class LBMRollout(torch.autograd.Function):
     """rho_T = LBMRollout.apply(rho0, sigma, width, tr, nsteps, every, options).
 
+    every is the checkpoint interval or "auto" (see choose_every).
+
     rho0 is an (ny, nx) CUDA tensor; sigma, width and tr are Python floats
     or scalar tensors (gradients are returned for tensors); options is a dict
     of further make_params keywords (s_p, varpi, ...) or None."""
@@ -126,7 +164,7 @@ class LBMRollout(torch.autograd.Function):
     @staticmethod
     def forward(ctx, rho0, sigma, width, tr, nsteps, every, options):
         ny, nx = rho0.shape
-        r = Rollout(nx, ny, int(nsteps), int(every), device=rho0.device, sigma=float(sigma), width=float(width),
+        r = Rollout(nx, ny, int(nsteps), every, device=rho0.device, sigma=float(sigma), width=float(width),
                     tr=float(tr), **dict(options or {}))
         out = r.forward(rho0.detach())
         ctx.rollout = r
@@ -142,6 +180,6 @@ class LBMRollout(torch.autograd.Function):
         return (drho0.to(ctx.rho_dtype), *params, None, None, None)
 
 
-def lbm_rollout(rho0, sigma, width, tr, nsteps, every=100, **options):
+def lbm_rollout(rho0, sigma, width, tr, nsteps, every="auto", **options):
     """Differentiable rho_T of an nsteps rollout from f^eq(rho0)."""
     return LBMRollout.apply(rho0, sigma, width, tr, nsteps, every, options)

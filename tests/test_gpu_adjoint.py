@@ -240,6 +240,22 @@ def test_rollout_gradient_params_match_finite_differences(rollout_case):
         assert dp[j] == pytest.approx(num, rel=1e-4), j
 
 
+def test_rollout_auto_interval_keeps_every_state():
+    """every = "auto" keeps every state for a small rollout, and gives the
+    bits of an explicit every = 1."""
+    nx, ny, steps = 48, 40, 30
+    _, co = params_pair(nx, ny, tr=0.8)
+    rho = wl.droplets(nx, ny, co.rho_g, co.rho_l, co.width, [(20, 22)], [9.0])
+    out = []
+    for every in ("auto", 1):
+        r = pkg.Rollout(nx, ny, steps, every, tr=0.8)
+        rho_T = r.forward(rho)
+        out.append((r.every, rho_T.cpu().numpy(), r.backward(2.0 * rho_T)[0].cpu().numpy()))
+        r.release()
+    assert out[0][0] == 1
+    assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[0][2], out[1][2])
+
+
 def test_autograd_function_matches_driver_and_is_deterministic(rollout_case):
     co, rho0, target, rho_T, drho0, dth, dp = rollout_case
     tgt = torch.tensor(target, device=DEV)
