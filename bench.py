@@ -14,6 +14,10 @@ Prints one JSON line:
   legs.fp16, .bf16   the same step with 2-byte storage of f (40 B/LU), the
                      ratio to FP32, and the coexistence-density error of a
                      relaxed flat interface against the Maxwell densities;
+                     these steps are bound by the vector ALU, and every step
+                     leg also carries `alu`, its vector-ALU roofline (lane-
+                     instructions per update from the committed rocprofv3 SQ
+                     summary times the update rate, against 39.3e12/s);
   legs.fwd_adjoint   checkpointed forward + adjoint over 1000 steps of the
                      2048^2 droplet-pair crop (T/T_c = 0.6, K = 100), the
                      adjoint kernel's own roofline, and the gradient error of
@@ -50,6 +54,13 @@ ADJ_BYTES_PER_LU = 124
 # rocprofv3 FETCH_SIZE / WRITE_SIZE summaries of each kernel on the 4096^2 workload
 PROFILE_TRAFFIC = {k: os.path.join(ROOT, "profiles", f"traffic_{k}_spinodal4096.json")
                    for k in ("step_f32", "step_f16", "step_bf16", "adjoint_f32")}
+# rocprofv3 SQ summaries: vector instructions per lattice update of each kernel
+PROFILE_VALU = {k: os.path.join(ROOT, "profiles", f"valu_{k}_spinodal4096.json")
+                for k in ("step_f32", "step_f16", "step_bf16", "adjoint_f32")}
+# Vector-ALU peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# = 39.3e12 lane-instructions per second (one FP32 FMA each: 78.6 TFLOP/s,
+# half the 157.3 TFLOP/s of packed FP32, which this build does not use).
+VALU_PEAK_TLANE = 256 * 4 * 16 * 2.4e9 / 1e12
 GOLDEN = os.path.join(ROOT, "tests", "golden", "droplet512_gradients.json")
 
 
@@ -65,14 +76,33 @@ def measured_traffic(kernel, n_nodes):
     """HBM bytes per launch of `kernel` on n_nodes from the committed
     rocprofv3 counter summary, if it was taken on the current kernel source
     and lattice size; else None."""
+    t = _profile(PROFILE_TRAFFIC[kernel], n_nodes)
+    return None if t is None else round(t["bytes_per_launch"])
+
+
+def _profile(path, n_nodes):
+    """A committed profile summary if it was taken on the current kernel
+    source and lattice size, else None."""
     try:
-        with open(PROFILE_TRAFFIC[kernel]) as fh:
+        with open(path) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha") != kernel_source_hash() or t.get("n_nodes") != n_nodes:
+    return t if t.get("kernel_sha") == kernel_source_hash() and t.get("n_nodes") == n_nodes else None
+
+
+def alu_roofline(kernel, n_nodes, mlups):
+    """Vector-ALU roofline of a kernel bound by it: the lane-instructions per
+    update counted by rocprofv3 times the measured update rate, against the
+    non-packed vector peak; None without a current SQ summary."""
+    t = _profile(PROFILE_VALU[kernel], n_nodes)
+    if t is None:
         return None
-    return round(t["bytes_per_launch"])
+    achieved = mlups * 1e6 * t["valu_lane_instr_per_lu"] / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 2), "peak": round(VALU_PEAK_TLANE, 2),
+            "unit": "T lane-instr/s", "frac": round(achieved / VALU_PEAK_TLANE, 4),
+            "valu_lane_instr_per_lu": round(t["valu_lane_instr_per_lu"], 1),
+            "valu_busy_profiled": round(t["valu_busy"], 3)}
 
 
 class Timer:
@@ -105,10 +135,12 @@ def step_leg(pkg, wl, timer, storage, n, steps, warmup, tr=0.7, width=10.0):
         raise RuntimeError(f"{storage} state diverged")
     per = ms / steps
     gbs = BYTES_PER_LU[storage] * n * n / (per * 1e-3) / 1e9
-    return d, rho0, {"mlups": round(n * n * steps / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(per, 5),
+    mlups = round(n * n * steps / (ms * 1e-3) / 1e6, 1)
+    kernel = "step_" + storage.replace("fp", "f")
+    return d, rho0, {"mlups": mlups, "ms_per_step": round(per, 5),
                      "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                      "algorithmic_bytes_per_lu": BYTES_PER_LU[storage],
-                     "traffic": measured_traffic("step_" + storage.replace("fp", "f"), n * n)}
+                     "traffic": measured_traffic(kernel, n * n), "alu": alu_roofline(kernel, n * n, mlups)}
 
 
 def coalescence_leg(pkg, wl, timer, storage, nx=16384, ny=8192, steps=200, warmup=20):
@@ -262,7 +294,8 @@ def adjoint_kernel_leg(pkg, wl, timer, torch, n=4096, reps=200, tr=0.7, width=10
     return {"workload": f"spinodal decomposition {n}x{n}, T/Tc={tr}, W={width}", "ms_per_step": round(ms, 5),
             "mlups": round(n * n / (ms * 1e-3) / 1e6, 1), "achieved_gbs": round(gbs, 1),
             "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_lu": ADJ_BYTES_PER_LU,
-            "traffic": measured_traffic("adjoint_f32", n * n)}
+            "traffic": measured_traffic("adjoint_f32", n * n),
+            "alu": alu_roofline("adjoint_f32", n * n, n * n / (ms * 1e-3) / 1e6)}
 
 
 def gradient_error(pkg, wl, timer, torch):

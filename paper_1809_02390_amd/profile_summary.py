@@ -11,9 +11,20 @@ M MiB reads and writes M MiB).  Writes a JSON file that ``bench.py`` reads
 as the ``traffic`` of its roofline, keyed by a hash of the kernel sources so
 that a stale measurement is not reported.
 
+Instruction counters (one ``--pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU
+... GRBM_GUI_ACTIVE`` run of ``profile_driver``): vector instructions per
+lattice update (SQ_INSTS_VALU counts wave instructions; times 64 lanes over
+the nodes of a launch) and the share of SIMD cycles with a vector
+instruction issued (SQ_ACTIVE_INST_VALU, in quad cycles, times 4 over
+256 CUs x 4 SIMDs x GRBM_GUI_ACTIVE / 8, the GRBM count being summed over
+the eight XCDs).  Written to a JSON file that ``bench.py`` reads for the
+vector-ALU roofline of the kernels bound by it.
+
 Usage:
     python -m paper_1809_02390_amd.profile_summary counters --fetch DIR --write DIR \
         --kernel step_kernel --storage-tag F32 --n-nodes 16777216 --copy-mib 1024 --out FILE
+    python -m paper_1809_02390_amd.profile_summary valu --sq DIR --kernel step_kernel \
+        --storage-tag F32 --n-nodes 16777216 --out FILE
     python -m paper_1809_02390_amd.profile_summary trace --stats FILE
 """
 from __future__ import annotations
@@ -88,6 +99,30 @@ def counters(a):
     print(json.dumps(doc, indent=1))
 
 
+def valu(a):
+    is_kernel = lambda k: a.kernel in k and (a.storage_tag is None or a.storage_tag in k)
+    per = {}
+    for r in _rows(a.sq):
+        if is_kernel(r["Kernel_Name"]):
+            d = per.setdefault(r["Dispatch_Id"], {})
+            d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    per = [d for d in per.values() if d.get("SQ_WAVES", 0.0) > 0]
+    if not per:
+        raise ValueError("no SQ rows for the kernel")
+    m = {k: sum(d[k] for d in per) / len(per) for k in per[0]}
+    doc = {
+        "kernel": a.kernel + (f"<{a.storage_tag}>" if a.storage_tag else ""),
+        "kernel_sha": kernel_source_hash(), "n_nodes": a.n_nodes, "dispatches": len(per),
+        "waves": m["SQ_WAVES"], "valu_instr_per_wave": m["SQ_INSTS_VALU"] / m["SQ_WAVES"],
+        "valu_lane_instr_per_lu": m["SQ_INSTS_VALU"] * 64.0 / a.n_nodes,
+        "valu_busy": m["SQ_ACTIVE_INST_VALU"] * 4.0 / (256 * 4 * m["GRBM_GUI_ACTIVE"] / 8.0),
+        "commands": a.command,
+    }
+    with open(a.out, "w") as fh:
+        json.dump(doc, fh, indent=1)
+    print(json.dumps(doc, indent=1))
+
+
 def short_name(name):
     """Kernel name without argument list and namespaces."""
     s = name[5:] if name.startswith("void ") else name
@@ -136,12 +171,19 @@ def main():
     c.add_argument("--algorithmic", type=float, default=None)
     c.add_argument("--out", required=True)
     c.add_argument("--command", action="append", default=[], help="the rocprofv3 command lines (recorded)")
+    v = sub.add_parser("valu")
+    v.add_argument("--sq", required=True)
+    v.add_argument("--kernel", required=True)
+    v.add_argument("--storage-tag", default=None)
+    v.add_argument("--n-nodes", type=int, required=True)
+    v.add_argument("--out", required=True)
+    v.add_argument("--command", action="append", default=[], help="the rocprofv3 command line (recorded)")
     t = sub.add_parser("trace")
     t.add_argument("--stats", required=True)
     t.add_argument("--dispatches", default=None, help="the kernel_trace.csv of the same run")
     t.add_argument("--min-total-us", type=float, default=100.0)
     a = ap.parse_args()
-    counters(a) if a.cmd == "counters" else trace(a)
+    {"counters": counters, "valu": valu, "trace": trace}[a.cmd](a)
 
 
 if __name__ == "__main__":
