@@ -116,7 +116,10 @@ int lbm_sigma_paper(double width, double tr, double a, double b, double r_gas,
                     double* sigma_out);
 
 /* Bytes of ONE distribution buffer (the caller provides two, A and B):
- * 9*nx*ny*4 for LBM_FP32, 9*nx*ny*2 for the 2-byte storages.  0 on error. */
+ * nine planes P elements apart, 9*P*4 for LBM_FP32 and 9*P*2 for the 2-byte
+ * storages, with P = nx*ny rounded up to a multiple of 64 plus 16640 bytes'
+ * worth of elements (16640/4 or 16640/2), so that the planes do not start
+ * at one offset modulo a large power of two.  0 on error. */
 size_t lbm_state_bytes(const lbm_params* p);
 
 /* Bytes of the reference-density buffer the 2-byte storages need (two
@@ -205,8 +208,8 @@ int lbm_step_saved_chain(lbm_ctx* ctx, void* const* bufs, int32_t n);
  * created and is summed and cleared by lbm_adjoint_theta.  Accumulation and
  * its sum run in a fixed order: repeated runs give identical bits. */
 
-/* Bytes of one adjoint state buffer (11*nx*ny*4); 0 for the 2-byte
- * storages or on error. */
+/* Bytes of one adjoint state buffer (11*P*4, P as for lbm_state_bytes with
+ * FP32 planes); 0 for the 2-byte storages or on error. */
 size_t lbm_adjoint_bytes(const lbm_params* p);
 
 /* adj := the adjoint state of Lambda = lam (device float, 9*nx*ny). */

@@ -148,6 +148,19 @@ __device__ __forceinline__ OutPlanes<E> out_planes(void* dst, size_t N) {
   return P;
 }
 
+// Elements from one plane of an internal buffer (A/B state, checkpoint,
+// adjoint state) to the next: nx*ny rounded up to 64, plus LBM_PLANE_PAD
+// bytes, so that the planes do not all start at one offset modulo a large
+// power of two (the streams of the nine planes then spread over the HBM
+// channels).  The 2-byte reference planes and the caller's plain arrays use
+// nx*ny.
+#ifndef LBM_PLANE_PAD
+#define LBM_PLANE_PAD 16640
+#endif
+__host__ __device__ __forceinline__ size_t plane_elems(int nx, int ny, int es) {
+  return ((size_t)nx * ny + 63) / 64 * 64 + (size_t)(LBM_PLANE_PAD / es);
+}
+
 // Raw stored values arriving at a node: raw_i = src_i(x - e_i).
 template <typename E>
 __device__ __forceinline__ void pull_raw(const Planes<E>& P, const NodeAddr<sizeof(E)>& a, E* r) {
@@ -392,7 +405,7 @@ __global__ __launch_bounds__(S::NTHREADS) void step_kernel(const void* __restric
   using E = typename St::E;
   __shared__ float srho[S::LDS];
   __shared__ float sref[St::kRef ? 3 * S::LDS : 1];
-  const size_t N = (size_t)nx * ny;
+  const size_t N = plane_elems(nx, ny, St::ES);
   int tx, ty;
   strip_tile(xcd_tile(blockIdx.x, ntiles), ntx, ntiles / ntx, strip, tx, ty);
   const int x0 = tx * S::TX, y0 = ty * S::TY;
@@ -449,7 +462,7 @@ __global__ __launch_bounds__(MomTile::NTHREADS) void moments_kernel(
   using S = MomTile;
   __shared__ float srho[S::LDS];
   __shared__ double sred[3][S::NTHREADS];
-  const size_t N = (size_t)nx * ny;
+  const size_t N = plane_elems(nx, ny, St::ES);
   const int x0 = (blockIdx.x % ntx) * S::TX, y0 = (blockIdx.x / ntx) * S::TY;
   float f[S::NPT][9];
   float rho[S::NPT];
@@ -519,7 +532,7 @@ template <class St>
 __device__ __forceinline__ void put_node(int x, int y, int nx, int ny, const float* f, const RefPoly<float>& q,
                                          void* dst, uint16_t* ref_out) {
   using E = typename St::E;
-  const size_t N = (size_t)nx * ny;
+  const size_t P = plane_elems(nx, ny, St::ES);
   float rd[9];
   if constexpr (St::kRef) {
     const float r = ref_density(density(f));
@@ -533,7 +546,7 @@ __device__ __forceinline__ void put_node(int x, int y, int nx, int ny, const flo
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const int xs = wrap(x - kCx[i], nx), ys = wrap(y - kCy[i], ny);
-    d[(size_t)i * N + (size_t)ys * nx + xs] = out[i];
+    d[(size_t)i * P + (size_t)ys * nx + xs] = out[i];
   }
 }
 
@@ -580,7 +593,7 @@ __global__ __launch_bounds__(BLK) void get_state_kernel(const void* __restrict__
   if (o >= N) return;
   const int x = (int)(o % nx), y = (int)(o / nx);
   E raw[9];
-  pull_raw<E>(planes<E>(src, N), node_addr<St::ES>(x, y, nx, ny), raw);
+  pull_raw<E>(planes<E>(src, plane_elems(nx, ny, St::ES)), node_addr<St::ES>(x, y, nx, ny), raw);
   float f[9];
   decode<St>(raw, St::kRef ? ref_in[o] : 0, q, f);
 #pragma unroll
@@ -714,7 +727,7 @@ template <class S, bool kInterior>
 __device__ __forceinline__ void adjoint_tile(const float* __restrict__ fsrc, const float* __restrict__ adj_in,
                                              float* __restrict__ adj_out, int nx, int ny, int x0, int y0,
                                              const Coef<float>& c, float* srho, float* snu, float* sa, float* th) {
-  const size_t N = (size_t)nx * ny;
+  const size_t N = plane_elems(nx, ny, 4);  // state and adjoint planes alike
   const Planes<float> P = planes<float>(adj_in, N);
   const unsigned rb = 4u * (unsigned)nx;
   const int x = x0 + threadIdx.x;
@@ -807,9 +820,9 @@ __global__ __launch_bounds__(S::NTHREADS) void adjoint_finish_kernel(
   using L = AdjLds<S>;
   __shared__ float snu[S::LDS];
   __shared__ __align__(8) float sa[L::NSA];
-  const size_t N = (size_t)nx * ny;
+  const size_t N = (size_t)nx * ny, P = plane_elems(nx, ny, 4);
   const int x0 = (blockIdx.x % ntx) * S::TX, y0 = (blockIdx.x / ntx) * S::TY;
-  stage_nu<S>(adj + 9 * N, adj + 10 * N, nx, ny, x0, y0, sa, snu);
+  stage_nu<S>(adj + 9 * P, adj + 10 * P, nx, ny, x0, y0, sa, snu);
   float th[3] = {0.0f, 0.0f, 0.0f};
   const int x = x0 + threadIdx.x;
 #pragma unroll
@@ -820,7 +833,7 @@ __global__ __launch_bounds__(S::NTHREADS) void adjoint_finish_kernel(
     const size_t o = (size_t)y * nx + x;
     float lam[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) lam[i] = adj[(size_t)i * N + o] + nu;
+    for (int i = 0; i < 9; ++i) lam[i] = adj[(size_t)i * P + o] + nu;
     if constexpr (kInit) {
       out[o] = equilibrium_vjp<float>(rho0[o], ux0 ? ux0[o] : 0.0f, uy0 ? uy0[o] : 0.0f, c, lam, th);
     } else {
@@ -831,15 +844,16 @@ __global__ __launch_bounds__(S::NTHREADS) void adjoint_finish_kernel(
   if constexpr (kInit) block_accumulate<S>(th, reinterpret_cast<double*>(sa), partials);
 }
 
-// Adjoint state from a plain Lambda: L = lam, A = 0.
+// Adjoint state (planes P elements apart) from a plain Lambda (planes N
+// apart): L = lam, A = 0.
 __global__ __launch_bounds__(BLK) void adjoint_seed_kernel(const float* __restrict__ lam, float* __restrict__ adj,
-                                                          size_t N) {
+                                                          size_t N, size_t P) {
   const size_t o = (size_t)blockIdx.x * BLK + threadIdx.x;
   if (o >= N) return;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) adj[(size_t)i * N + o] = lam[(size_t)i * N + o];
-  adj[9 * N + o] = 0.0f;
-  adj[10 * N + o] = 0.0f;
+  for (int i = 0; i < 9; ++i) adj[(size_t)i * P + o] = lam[(size_t)i * N + o];
+  adj[9 * P + o] = 0.0f;
+  adj[10 * P + o] = 0.0f;
 }
 
 // ---------------------------------------------------------------------------
@@ -1068,7 +1082,8 @@ int lbm_sigma_paper(double width, double tr, double a, double b, double r_gas, d
 size_t lbm_state_bytes(const lbm_params* p) {
   char msg[256];
   if (lbm::validate(p, msg, sizeof msg)) return 0;
-  return (size_t)9 * p->nx * p->ny * (p->storage == LBM_FP32 ? 4 : 2);
+  const int es = p->storage == LBM_FP32 ? 4 : 2;
+  return (size_t)9 * plane_elems(p->nx, p->ny, es) * es;
 }
 
 size_t lbm_ref_bytes(const lbm_params* p) {
@@ -1297,7 +1312,7 @@ int lbm_step_saved_chain(lbm_ctx* ctx, void* const* bufs, int32_t n) {
 size_t lbm_adjoint_bytes(const lbm_params* p) {
   char msg[256];
   if (lbm::validate(p, msg, sizeof msg) || p->storage != LBM_FP32) return 0;
-  return (size_t)11 * p->nx * p->ny * sizeof(float);
+  return (size_t)11 * plane_elems(p->nx, p->ny, 4) * sizeof(float);
 }
 
 int lbm_adjoint_seed(lbm_ctx* ctx, const float* lam, void* adj) {
@@ -1306,7 +1321,8 @@ int lbm_adjoint_seed(lbm_ctx* ctx, const float* lam, void* adj) {
   if (!lam || !adj) return fail(LBM_EINVAL, "lam and adj must be device buffers");
   if (int st = set_device(ctx)) return st;
   const size_t N = (size_t)ctx->p.nx * ctx->p.ny;
-  adjoint_seed_kernel<<<grid1(N), BLK, 0, ctx->stream>>>(lam, static_cast<float*>(adj), N);
+  adjoint_seed_kernel<<<grid1(N), BLK, 0, ctx->stream>>>(lam, static_cast<float*>(adj), N,
+                                                        plane_elems(ctx->p.nx, ctx->p.ny, 4));
   HIP_OK(hipGetLastError());
   return LBM_OK;
 }

@@ -231,13 +231,13 @@ def lbm_step_saved_chain(ctx, bufs, nbytes):
     _check(_lib.lbm_step_saved_chain(ctx, _ptr_array(bufs, nbytes, "bufs"), len(bufs) - 1))
 
 
-def lbm_adjoint_run(ctx, f_states, adj_a, adj_b, n, state_bytes):
+def lbm_adjoint_run(ctx, f_states, adj_a, adj_b, state_bytes, adj_bytes):
     """Adjoint steps back through f_states; returns 0 or 1: which of adj_a,
     adj_b holds the result."""
     which = ctypes.c_int32(-1)
     arr = _ptr_array(f_states, state_bytes, "f_states")
-    _check(_lib.lbm_adjoint_run(ctx, arr, len(f_states), _bytes_ptr(adj_a, 44 * n, "adj_a"),
-                                _bytes_ptr(adj_b, 44 * n, "adj_b"), ctypes.byref(which)))
+    _check(_lib.lbm_adjoint_run(ctx, arr, len(f_states), _bytes_ptr(adj_a, adj_bytes, "adj_a"),
+                                _bytes_ptr(adj_b, adj_bytes, "adj_b"), ctypes.byref(which)))
     return which.value
 
 
@@ -245,22 +245,22 @@ def lbm_adjoint_bytes(params: lbm_params) -> int:
     return _lib.lbm_adjoint_bytes(ctypes.byref(params))
 
 
-def lbm_adjoint_seed(ctx, lam, adj, n):
-    _check(_lib.lbm_adjoint_seed(ctx, _ptr(lam, torch.float32, 9 * n, "lam"), _bytes_ptr(adj, 44 * n, "adj")))
+def lbm_adjoint_seed(ctx, lam, adj, n, adj_bytes):
+    _check(_lib.lbm_adjoint_seed(ctx, _ptr(lam, torch.float32, 9 * n, "lam"), _bytes_ptr(adj, adj_bytes, "adj")))
 
 
-def lbm_adjoint_step(ctx, f_t, adj_next, adj_out, n, state_bytes):
-    _check(_lib.lbm_adjoint_step(ctx, _bytes_ptr(f_t, state_bytes, "f_t"), _bytes_ptr(adj_next, 44 * n, "adj_next"),
-                                 _bytes_ptr(adj_out, 44 * n, "adj_out")))
+def lbm_adjoint_step(ctx, f_t, adj_next, adj_out, state_bytes, adj_bytes):
+    _check(_lib.lbm_adjoint_step(ctx, _bytes_ptr(f_t, state_bytes, "f_t"), _bytes_ptr(adj_next, adj_bytes, "adj_next"),
+                                 _bytes_ptr(adj_out, adj_bytes, "adj_out")))
 
 
-def lbm_adjoint_get(ctx, adj, lam, n):
-    _check(_lib.lbm_adjoint_get(ctx, _bytes_ptr(adj, 44 * n, "adj"), _ptr(lam, torch.float32, 9 * n, "lam")))
+def lbm_adjoint_get(ctx, adj, lam, n, adj_bytes):
+    _check(_lib.lbm_adjoint_get(ctx, _bytes_ptr(adj, adj_bytes, "adj"), _ptr(lam, torch.float32, 9 * n, "lam")))
 
 
-def lbm_adjoint_init(ctx, rho0, ux0, uy0, adj0, drho0, n):
+def lbm_adjoint_init(ctx, rho0, ux0, uy0, adj0, drho0, n, adj_bytes):
     _check(_lib.lbm_adjoint_init(ctx, _ptr(rho0, torch.float32, n, "rho0"), _ptr(ux0, torch.float32, n, "ux0"),
-                                 _ptr(uy0, torch.float32, n, "uy0"), _bytes_ptr(adj0, 44 * n, "adj0"),
+                                 _ptr(uy0, torch.float32, n, "uy0"), _bytes_ptr(adj0, adj_bytes, "adj0"),
                                  _ptr(drho0, torch.float32, n, "drho0")))
 
 
@@ -368,11 +368,12 @@ class Lattice:
     def adjoint_seed(self, lam, adj=None):
         adj = self.adjoint_buffer() if adj is None else adj
         lam = torch.as_tensor(lam, dtype=torch.float32).to(self.f_a.device).contiguous()
-        lbm_adjoint_seed(self.ctx, lam, adj, self.n)
+        lbm_adjoint_seed(self.ctx, lam, adj, self.n, lbm_adjoint_bytes(self.params))
         return adj
 
     def adjoint_step(self, f_t, adj_next, adj_out):
-        lbm_adjoint_step(self.ctx, f_t, adj_next, adj_out, self.n, lbm_checkpoint_bytes(self.params))
+        lbm_adjoint_step(self.ctx, f_t, adj_next, adj_out, lbm_checkpoint_bytes(self.params),
+                         lbm_adjoint_bytes(self.params))
         return adj_out
 
     def step_saved_chain(self, bufs):
@@ -380,12 +381,13 @@ class Lattice:
 
     def adjoint_run(self, f_states, adj_a, adj_b):
         """Adjoint steps back through f_states; returns the buffer holding the result."""
-        w = lbm_adjoint_run(self.ctx, f_states, adj_a, adj_b, self.n, lbm_checkpoint_bytes(self.params))
+        w = lbm_adjoint_run(self.ctx, f_states, adj_a, adj_b, lbm_checkpoint_bytes(self.params),
+                            lbm_adjoint_bytes(self.params))
         return adj_a if w == 0 else adj_b
 
     def adjoint_get(self, adj):
         lam = torch.empty((9, self.ny, self.nx), dtype=torch.float32, device=self.f_a.device)
-        lbm_adjoint_get(self.ctx, adj, lam, self.n)
+        lbm_adjoint_get(self.ctx, adj, lam, self.n, lbm_adjoint_bytes(self.params))
         return lam
 
     def adjoint_init(self, rho0, adj0, ux0=None, uy0=None):
@@ -393,7 +395,7 @@ class Lattice:
         conv = lambda a: None if a is None else torch.as_tensor(a, dtype=torch.float32).to(dev).contiguous()
         rho0, ux0, uy0 = conv(rho0), conv(ux0), conv(uy0)
         drho0 = torch.empty((self.ny, self.nx), dtype=torch.float32, device=dev)
-        lbm_adjoint_init(self.ctx, rho0, ux0, uy0, adj0, drho0, self.n)
+        lbm_adjoint_init(self.ctx, rho0, ux0, uy0, adj0, drho0, self.n, lbm_adjoint_bytes(self.params))
         return drho0
 
     def adjoint_theta(self, reset=True):

@@ -62,3 +62,13 @@ def device_samples(f_dev, points):
     xs = torch.tensor([p[0] for p in points], device=f_dev.device)
     ys = torch.tensor([p[1] for p in points], device=f_dev.device)
     return f_dev[:, ys, xs].T.double().cpu().numpy()
+
+
+def planes_of(buf, nx, ny, nplanes, es=4):
+    """The nplanes data regions (nplanes, ny*nx) of an internal byte buffer
+    (state, checkpoint or adjoint state): planes P elements apart, with P =
+    nx*ny rounded up to 64 plus 16640 bytes' worth of elements (include/lbm.h);
+    the padding between planes holds no data."""
+    p = -(-nx * ny // 64) * 64 + 16640 // es
+    dtype = torch.float32 if es == 4 else torch.int16
+    return buf[: nplanes * p * es].view(dtype).reshape(nplanes, p)[:, : nx * ny]

@@ -68,19 +68,25 @@ def test_invalid_parameters_rejected(bad):
     assert pkg.lbm_state_bytes(pkg.make_params(nx, ny, **kw)) == 0
 
 
+def plane(nx, ny, es):
+    """Elements between planes of an internal buffer: nx*ny rounded up to 64
+    plus a 16640-byte pad (include/lbm.h)."""
+    return -(-nx * ny // 64) * 64 + 16640 // es
+
+
 def test_buffer_sizes():
     p = pkg.make_params(100, 30)
-    assert pkg.lbm_state_bytes(p) == 9 * 100 * 30 * 4
+    assert pkg.lbm_state_bytes(p) == 9 * plane(100, 30, 4) * 4
     assert pkg.lbm_ref_bytes(p) == 0
     p16 = pkg.make_params(100, 30, storage="fp16")
-    assert pkg.lbm_state_bytes(p16) == 9 * 100 * 30 * 2
+    assert pkg.lbm_state_bytes(p16) == 9 * plane(100, 30, 2) * 2
     assert pkg.lbm_ref_bytes(p16) == 2 * 100 * 30 * 2
 
 
 def test_largest_lattice_accepted():
     """9 nx ny < 2^31 is the size limit: 16384 x 14563 (9 nx ny = 2147401728)
     is accepted, one row more is not."""
-    assert pkg.lbm_state_bytes(pkg.make_params(16384, 14563)) == 9 * 16384 * 14563 * 4
+    assert pkg.lbm_state_bytes(pkg.make_params(16384, 14563)) == 9 * plane(16384, 14563, 4) * 4
     assert pkg.lbm_state_bytes(pkg.make_params(16384, 14564)) == 0
 
 
@@ -91,10 +97,10 @@ def test_null_context_rejected():
 
 def test_checkpoint_and_adjoint_sizes():
     p = pkg.make_params(100, 30)
-    assert pkg.lbm_checkpoint_bytes(p) == 9 * 100 * 30 * 4
-    assert pkg.lbm_adjoint_bytes(p) == 11 * 100 * 30 * 4
+    assert pkg.lbm_checkpoint_bytes(p) == 9 * plane(100, 30, 4) * 4
+    assert pkg.lbm_adjoint_bytes(p) == 11 * plane(100, 30, 4) * 4
     p16 = pkg.make_params(100, 30, storage="bf16")
-    assert pkg.lbm_checkpoint_bytes(p16) == 9 * 100 * 30 * 2 + 100 * 30 * 2
+    assert pkg.lbm_checkpoint_bytes(p16) == 9 * plane(100, 30, 2) * 2 + 100 * 30 * 2
     assert pkg.lbm_adjoint_bytes(p16) == 0  # the adjoint is FP32-only
     assert pkg.lbm_checkpoint_bytes(pkg.make_params(0, 3)) == 0
 

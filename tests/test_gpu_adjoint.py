@@ -22,7 +22,7 @@ import workloads as wl
 from oracle import adjoint as adj
 from oracle import hostmap as hm
 from oracle import lbm
-from tests._gpu_helpers import oracle_init, params_pair
+from tests._gpu_helpers import oracle_init, params_pair, planes_of
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -136,7 +136,7 @@ def test_step_saved_is_bitwise_lbm_step():
         lat.step_saved(bufs[k % 2], bufs[(k + 1) % 2])
     lat.step(5)
     lat.save_state(bufs[2])
-    assert torch.equal(bufs[1], bufs[2])
+    assert torch.equal(planes_of(bufs[1], nx, ny, 9), planes_of(bufs[2], nx, ny, 9))
 
 
 def test_native_segment_calls_match_single_steps():
@@ -151,7 +151,7 @@ def test_native_segment_calls_match_single_steps():
     single = [chain[0]] + [lat.checkpoint_buffer() for _ in range(n)]
     for j in range(n):
         lat.step_saved(single[j], single[j + 1])
-    assert all(torch.equal(a, b) for a, b in zip(chain, single))
+    assert all(torch.equal(planes_of(a, nx, ny, 9), planes_of(b, nx, ny, 9)) for a, b in zip(chain, single))
     lam = np.random.default_rng(3).standard_normal((9, ny, nx))
     a, b = lat.adjoint_seed(lam), lat.adjoint_buffer()
     lat.adjoint_theta(reset=True)
@@ -162,7 +162,7 @@ def test_native_segment_calls_match_single_steps():
         lat.adjoint_step(chain[j], x, y)
         x, y = y, x
     th_single = lat.adjoint_theta(reset=True)
-    assert out is b and torch.equal(out, x) and th_run == th_single
+    assert out is b and torch.equal(planes_of(out, nx, ny, 11), planes_of(x, nx, ny, 11)) and th_run == th_single
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
