@@ -35,7 +35,6 @@ Prints one JSON line:
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -65,11 +64,10 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "droplet512_gradients.json")
 
 
 def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("lbm_kernels.hip", "lbm_cell.h"):
-        with open(os.path.join(ROOT, "paper_1809_02390_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    """The profile summaries' hash of the kernel sources (comments ignored)."""
+    sys.path.insert(0, ROOT)
+    from paper_1809_02390_amd.profile_summary import kernel_source_hash as h
+    return h()
 
 
 def measured_traffic(kernel, n_nodes):

@@ -11,9 +11,12 @@
  * ---------------------------------------
  *  - Lattice units: dx = dt = c = 1, c_s^2 = 1/3.  Periodic in x and y.
  *  - Fields are row-major with x fastest: element (y, x) of an ny-by-nx
- *    field sits at offset y*nx + x.  Distribution arrays are structure-of-
- *    arrays, population i (velocity order of supplement Eq. 3: rest, +x, +y,
- *    -x, -y, +x+y, -x+y, -x-y, +x-y) at offset i*nx*ny.
+ *    field sits at offset y*nx + x.  Distribution arrays passed as plain
+ *    float arrays (f, lam) are structure-of-arrays, population i (velocity
+ *    order of supplement Eq. 3: rest, +x, +y, -x, -y, +x+y, -x+y, -x-y,
+ *    +x-y) at offset i*nx*ny.  The library's own buffers (A/B states,
+ *    checkpoints, adjoint states) have internal layouts; size them with the
+ *    *_bytes calls.
  *  - Field and buffer pointers (f, f_*, rho*, u*, lam, adj*, drho0, src,
  *    dst) are DEVICE pointers owned by the caller (any allocator; the
  *    library never frees them).  The result pointers out, sigma_out,
@@ -200,7 +203,7 @@ int lbm_step_saved_chain(lbm_ctx* ctx, void* const* bufs, int32_t n);
  * theta = (G'^2, K', R T).
  *
  * Adjoint states live in caller-owned device buffers of lbm_adjoint_bytes
- * (eleven FP32 planes of nx*ny in an internal layout: Lambda is held as nine
+ * (eleven FP32 planes in an internal layout: Lambda is held as nine
  * planes plus the two-component adjoint of the force-stencil gradient, which
  * the next step scatters to the neighbour densities).  lbm_adjoint_seed and
  * lbm_adjoint_get convert from and to plain Lambda arrays in the SoA layout

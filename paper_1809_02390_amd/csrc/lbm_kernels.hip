@@ -1,8 +1,11 @@
 // HIP kernels and C-ABI entry points of the self-tuning-EOS D2Q9 library
 // (gfx950).  See include/lbm.h for the contract of every entry point.
 //
-// Data layout: structure of arrays, population i at offset i*nx*ny, x
-// fastest.  Two caller-owned buffers A and B alternate; the buffer that is
+// Data layout: structure of arrays, x fastest, population i at offset
+// i*P with P = plane_elems (nx*ny rounded up to 64 plus a pad, so that the
+// planes do not start at one offset modulo a large power of two); the
+// caller's plain arrays use P = nx*ny.  Two caller-owned buffers A and B
+// alternate; the buffer that is
 // read by the next step holds the post-collision populations of the previous
 // step at their source node ("pull" streaming: f_i(x, t) = src_i(x - e_i)).
 //

@@ -35,15 +35,21 @@ import glob
 import hashlib
 import json
 import os
+import re
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources with comments and whitespace removed, so
+    that a profile stays current across edits that change no code."""
     h = hashlib.sha256()
     for f in ("lbm_kernels.hip", "lbm_cell.h"):
-        with open(os.path.join(PKG, "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(PKG, "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 
