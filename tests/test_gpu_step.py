@@ -268,6 +268,29 @@ def test_sampled_parity_largest_lattice():
     assert np.abs(got - ref).max() / co.rho_l <= TOL
 
 
+def test_two_lattices_on_two_streams_match_single_runs():
+    """Every launch goes to its context's stream and contexts share no device
+    state: two lattices (FP32 and FP16) stepped in turn on two streams end
+    with the bits of the same runs made alone on the default stream."""
+    nx, ny, chunks = 300, 200, 10
+    _, co = params_pair(nx, ny, tr=0.7, width=10.0)
+    rho_a = wl.droplets(nx, ny, co.rho_g, co.rho_l, co.width, [(100, 90)], [30.0])
+    rho_b = wl.droplets(nx, ny, co.rho_g, co.rho_l, co.width, [(200, 120), (60, 50)], [25.0, 20.0])
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    la = pkg.Lattice(nx, ny, stream=sa, tr=0.7, width=10.0).init(rho_a)
+    lb = pkg.Lattice(nx, ny, stream=sb, tr=0.7, width=10.0, storage="fp16").init(rho_b)
+    for _ in range(chunks):
+        la.step(20)
+        lb.step(20)
+    torch.cuda.synchronize()
+    got = (la.state(), lb.state())
+    torch.cuda.synchronize()
+    ref_a = pkg.Lattice(nx, ny, tr=0.7, width=10.0).init(rho_a).step(20 * chunks).state()
+    ref_b = pkg.Lattice(nx, ny, tr=0.7, width=10.0, storage="fp16").init(rho_b).step(20 * chunks).state()
+    torch.cuda.synchronize()
+    assert torch.equal(got[0], ref_a) and torch.equal(got[1], ref_b)
+
+
 def test_laplace_law_256():
     """Static droplets R = 20..60 on 256^2 (T_r = 0.8, W = 10, sigma_paper),
     relaxed for 80000 steps (the breathing mode has decayed by 60000): the
