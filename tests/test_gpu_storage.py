@@ -61,11 +61,12 @@ def test_step_parity_within_storage_precision(storage):
 
 
 @pytest.mark.parametrize("storage", STORAGES)
-@pytest.mark.parametrize("nx,ny", [(70, 37), (400, 37)])
+@pytest.mark.parametrize("nx,ny", [(70, 37), (400, 37), (1300, 410)])
 def test_ragged_lattice_runs_and_matches_fp32(storage, nx, ny):
     """Ragged tiles: the 2-byte run stays within storage precision of FP32;
     400 x 37 also has interior tiles (the fast addressing path) next to
-    edge tiles."""
+    edge tiles, and 1300 x 410 runs the 128 x 8 tiles of the large
+    workloads (smaller lattices run 64 x 4 tiles)."""
     _, co = params_pair(nx, ny, tr=0.8)
     centres, radii = [(30, 20)], [11.0]
     if nx > 200:  # a second droplet inside the interior tiles
