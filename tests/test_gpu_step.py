@@ -294,17 +294,21 @@ def test_two_lattices_on_two_streams_match_single_runs():
     assert torch.equal(got[0], ref_a) and torch.equal(got[1], ref_b)
 
 
-def test_laplace_law_256():
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
+def test_laplace_law_256(storage):
     """Static droplets R = 20..60 on 256^2 (T_r = 0.8, W = 10, sigma_paper),
     relaxed for 80000 steps (the breathing mode has decayed by 60000): the
     fitted slope of Delta p against 1/R over R >= 30 matches sigma within 3%,
     each R >= 40 within 3%, R = 20 within 10% (W/R = 0.5).  Spurious currents
-    (no bound in the paper) must stay below 1e-3 in lattice units."""
+    (no bound in the paper) must stay below 1e-3 in lattice units.  FP16
+    storage keeps every bound.  BF16 storage (8-bit significand) keeps them
+    for R >= 30; its R = 20 droplet dissolves further (radius about 13 against
+    about 15 in FP32), so there it must only survive, with its ratio reported."""
     n = 256
     _, co = params_pair(n, n, tr=0.8, width=10.0)
     inv_r, dps, report = [], [], []
     for R in (20, 30, 40, 50, 60):
-        lat = lattice(n, n, wl.static_droplet(co, n, R), tr=0.8, width=10.0)
+        lat = lattice(n, n, wl.static_droplet(co, n, R), tr=0.8, width=10.0, storage=storage)
         lat.step(80000)
         r, ux, uy, _ = lat.moments()
         r = r.double().cpu().numpy()
@@ -314,12 +318,15 @@ def test_laplace_law_256():
             inv_r.append(1.0 / radius)
             dps.append(dp)
         report.append((R, round(radius, 3), round(sigma / co.sigma, 4), umax))
-    print("R, measured R, sigma/sigma_prescribed, max|u|:", report)
+    print(storage, "R, measured R, sigma/sigma_prescribed, max|u|:", report)
     slope = np.polyfit(inv_r, dps, 1)[0]
     assert slope == pytest.approx(co.sigma, rel=0.03), (slope / co.sigma, report)
-    for R, _, ratio, umax in report:
-        assert ratio == pytest.approx(1.0, abs=0.03 if R >= 40 else 0.10), report
+    for R, radius, ratio, umax in report:
         assert umax < 1e-3, report
+        if storage == "bf16" and R == 20:
+            assert radius > 10.0, report
+            continue
+        assert ratio == pytest.approx(1.0, abs=0.03 if R >= 40 else 0.10), report
 
 
 def test_coexistence_and_width_gpu():
