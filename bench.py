@@ -58,7 +58,7 @@ PROFILE_VALU = {k: os.path.join(ROOT, "profiles", f"valu_{k}_spinodal4096.json")
                 for k in ("step_f32", "step_f16", "step_bf16", "adjoint_f32")}
 # Vector-ALU peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # = 39.3e12 lane-instructions per second (one FP32 FMA each: 78.6 TFLOP/s,
-# half the 157.3 TFLOP/s of packed FP32, which this build does not use).
+# half the 157.3 TFLOP/s of packed FP32, which the library is compiled without).
 VALU_PEAK_TLANE = 256 * 4 * 16 * 2.4e9 / 1e12
 GOLDEN = os.path.join(ROOT, "tests", "golden", "droplet512_gradients.json")
 
@@ -372,7 +372,7 @@ def main():
     ap.add_argument("--only-fp32", action="store_true", help="skip the 2-byte and adjoint legs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               "(the lattice would shard as row slabs with a halo exchange per step)", file=sys.stderr)
         sys.exit(2)
 
