@@ -125,43 +125,87 @@ def test_collision_matrix_inverse_printed(co):
         np.testing.assert_allclose(S @ Si, np.eye(9), atol=1e-14)
 
 
+def cubic_residuals(c, R, T, X, sample):
+    """Correction terms of rows e, p_xx, p_xy plus the cubic velocity terms
+    printed in supplement Eqs. 33, 36 and 39, with the leading-order
+    relations of supplement Eq. 32 for G-hat_1,7,8 (c = dt = 1); zero when
+    R, T, X are right."""
+    k, h, b, vp, se, sp = c.k, c.h, c.bs, c.varpi, c.s_e, c.s_p
+    ux, uy, rho, drx, dry, dpx, dpy, uxx, uyy, uxy, uyx = sample
+    div, dif, sxy = uxx + uyy, uxx - uyy, uxy + uyx
+    G1 = -(2 - se) / (2 * se) * 2 * vp * rho * div
+    G7 = -(2 - sp) / (2 * sp) * 2 / 3 * rho * dif
+    G8 = -(2 - sp) / (2 * sp) * 1 / 3 * rho * sxy
+
+    def corr(r, s):
+        return 2 / (2 - s) * (R[r, 1] * G1 + R[r, 7] * G7 + R[r, 8] * G8
+                              + T[r, 0] * drx + T[r, 1] * dry + X[r, 0] * dpx + X[r, 1] * dpy)
+
+    cub1 = (-(9 * (2 * k + h) * ux * uy ** 2 * dpx + 9 * (2 * k + h) * ux ** 2 * uy * dpy)
+            - (3 * ((1 - k) * ux ** 3 - (2 * k + h) * ux * uy ** 2) * drx
+               + 3 * ((1 - k) * uy ** 3 - (2 * k + h) * ux ** 2 * uy) * dry)
+            - ((9 * (1 - k) * ux ** 2 - 2 * (3 * k + h) * uy ** 2) * rho * uxx
+               + (9 * (1 - k) * uy ** 2 - 2 * (3 * k + h) * ux ** 2) * rho * uyy
+               - 4 * (3 * k + h) * ux * uy * rho * sxy))
+    cub7 = ((6 * b * ux * uy ** 2 * dpx - 6 * b * ux ** 2 * uy * dpy)
+            - ((ux ** 3 + 2 * b * ux * uy ** 2) * drx - (uy ** 3 + 2 * b * ux ** 2 * uy) * dry)
+            - ((3 * ux ** 2 + 4 * b * uy ** 2) * rho * uxx - (3 * uy ** 2 + 4 * b * ux ** 2) * rho * uyy))
+    cub8 = (-(3 * b * (uy ** 3 + 2 * ux ** 2 * uy) * dpx + 3 * b * (ux ** 3 + 2 * ux * uy ** 2) * dpy)
+            + (b * (uy ** 3 + 2 * ux ** 2 * uy) * drx + b * (ux ** 3 + 2 * ux * uy ** 2) * dry)
+            + (2 * b * ux * uy * rho * uxx + 2 * b * ux * uy * rho * uyy
+               + 2 * b * (ux ** 2 + uy ** 2) * rho * sxy))
+    return corr(1, se) + cub1, corr(7, sp) + cub7, corr(8, sp) + cub8
+
+
+def correction_samples(n=10):
+    out = []
+    for _ in range(n):
+        v = rng.uniform(-1, 1, 11)
+        v[2] = abs(v[2]) + 0.1  # rho
+        out.append(v)
+    return out
+
+
+# the entries of supplement Eqs. 34, 37, 40 that are not identically zero
+CORRECTION_ENTRIES = ([("R", r, q) for r, q in [(1, 1), (1, 7), (1, 8), (7, 1), (7, 7), (8, 1), (8, 8)]]
+                      + [(m, r, q) for m in ("T", "X") for r in (1, 7, 8) for q in (0, 1)])
+
+
 @pytest.mark.parametrize("s_p", [0.8, 1.0, 1.6])
 def test_corrections_cancel_printed_cubic_terms(s_p):
     """With the leading-order relations of supplement Eq. 32 for G-hat_1,7,8,
     the R, T, X terms cancel the cubic velocity terms printed in supplement
-    Eqs. 33, 36 and 39 exactly (c = dt = 1)."""
+    Eqs. 33, 36 and 39 exactly (c = dt = 1), and no other entry is nonzero."""
     c = hm.derive(hm.Params(tr=0.7, width=10.0, s_p=s_p))
-    k, h, b, vp, se, sp = c.k, c.h, c.bs, c.varpi, c.s_e, c.s_p
-    for _ in range(10):
-        ux, uy, rho, drx, dry, dpx, dpy, uxx, uyy, uxy, uyx = rng.uniform(-1, 1, 11)
-        rho = abs(rho) + 0.1
-        R, T, X = lbm.correction_matrices(np.array(ux), np.array(uy), c)
-        div, dif, sxy = uxx + uyy, uxx - uyy, uxy + uyx
-        G1 = -(2 - se) / (2 * se) * 2 * vp * rho * div
-        G7 = -(2 - sp) / (2 * sp) * 2 / 3 * rho * dif
-        G8 = -(2 - sp) / (2 * sp) * 1 / 3 * rho * sxy
+    for v in correction_samples():
+        R, T, X = lbm.correction_matrices(np.array(v[0]), np.array(v[1]), c)
+        for res in cubic_residuals(c, R, T, X, v):
+            assert res == pytest.approx(0.0, abs=1e-12)
+        # every other entry is zero: R acts only on the rows and columns of
+        # e, p_xx, p_xy (with R_78 = R_87 = 0), T and X only on those rows
+        nonzero = np.zeros((9, 9), dtype=bool)
+        nonzero[[1, 1, 1, 7, 7, 8, 8], [1, 7, 8, 1, 7, 1, 8]] = True
+        assert np.all(R[~nonzero] == 0)
+        others = [0, 2, 3, 4, 5, 6]
+        assert np.all(T[others] == 0) and np.all(X[others] == 0)
 
-        def corr(r, s):
-            return 2 / (2 - s) * (R[r, 1] * G1 + R[r, 7] * G7 + R[r, 8] * G8
-                                  + T[r, 0] * drx + T[r, 1] * dry + X[r, 0] * dpx + X[r, 1] * dpy)
 
-        cub1 = (-(9 * (2 * k + h) * ux * uy ** 2 * dpx + 9 * (2 * k + h) * ux ** 2 * uy * dpy)
-                - (3 * ((1 - k) * ux ** 3 - (2 * k + h) * ux * uy ** 2) * drx
-                   + 3 * ((1 - k) * uy ** 3 - (2 * k + h) * ux ** 2 * uy) * dry)
-                - ((9 * (1 - k) * ux ** 2 - 2 * (3 * k + h) * uy ** 2) * rho * uxx
-                   + (9 * (1 - k) * uy ** 2 - 2 * (3 * k + h) * ux ** 2) * rho * uyy
-                   - 4 * (3 * k + h) * ux * uy * rho * sxy))
-        cub7 = ((6 * b * ux * uy ** 2 * dpx - 6 * b * ux ** 2 * uy * dpy)
-                - ((ux ** 3 + 2 * b * ux * uy ** 2) * drx - (uy ** 3 + 2 * b * ux ** 2 * uy) * dry)
-                - ((3 * ux ** 2 + 4 * b * uy ** 2) * rho * uxx - (3 * uy ** 2 + 4 * b * ux ** 2) * rho * uyy))
-        cub8 = (-(3 * b * (uy ** 3 + 2 * ux ** 2 * uy) * dpx + 3 * b * (ux ** 3 + 2 * ux * uy ** 2) * dpy)
-                + (b * (uy ** 3 + 2 * ux ** 2 * uy) * drx + b * (ux ** 3 + 2 * ux * uy ** 2) * dry)
-                + (2 * b * ux * uy * rho * uxx + 2 * b * ux * uy * rho * uyy
-                   + 2 * b * (ux ** 2 + uy ** 2) * rho * sxy))
-        assert corr(1, se) + cub1 == pytest.approx(0.0, abs=1e-12)
-        assert corr(7, sp) + cub7 == pytest.approx(0.0, abs=1e-12)
-        assert corr(8, sp) + cub8 == pytest.approx(0.0, abs=1e-12)
-        assert R[7, 8] == 0 and R[8, 7] == 0
+@pytest.mark.parametrize("mistake", ["sign", "dropped", "factor"])
+def test_cancellation_detects_a_wrong_entry(mistake):
+    """The pin has power: a sign error, a dropped entry or a wrong factor in
+    any single nonzero entry of R, T or X (planted in the oracle's output)
+    leaves a residual."""
+    c = hm.derive(hm.Params(tr=0.7, width=10.0))
+    scale = {"sign": -1.0, "dropped": 0.0, "factor": 2.0}[mistake]
+    samples = correction_samples(4)
+    for name, r, q in CORRECTION_ENTRIES:
+        worst = 0.0
+        for v in samples:
+            R, T, X = lbm.correction_matrices(np.array(v[0]), np.array(v[1]), c)
+            mats = {"R": R.copy(), "T": T.copy(), "X": X.copy()}
+            mats[name][r, q] *= scale
+            worst = max(worst, max(abs(x) for x in cubic_residuals(c, mats["R"], mats["T"], mats["X"], v)))
+        assert worst > 1e-6, (name, r, q, mistake)
 
 
 # ---------------------------------------------------------------------------
