@@ -19,11 +19,14 @@ def totals(f):
 
 def level_crossings(profile, level):
     """Positions where a periodic 1-D profile crosses ``level``, by linear
-    interpolation between neighbouring nodes."""
+    interpolation between neighbouring nodes; a node exactly on the level is
+    a crossing at that node."""
     p = np.asarray(profile, dtype=np.float64)
-    q = np.roll(p, -1)
-    idx = np.nonzero((p - level) * (q - level) < 0)[0]
-    return idx + (level - p[idx]) / (q[idx] - p[idx])
+    a = p - level
+    b = np.roll(a, -1)
+    on = np.nonzero(a == 0)[0].astype(np.float64)  # a node exactly on the level
+    idx = np.nonzero(a * b < 0)[0]
+    return np.sort(np.concatenate([on, idx + a[idx] / (a[idx] - b[idx])]))
 
 
 def interface_width(profile, rho_g, rho_l):

@@ -105,6 +105,28 @@ def test_consistency_term_flux_is_r_add():
     np.testing.assert_array_equal(Q[[0, 3, 4, 5, 6]], 0.0)
 
 
+def test_consistency_term_is_second_order():
+    """The populations M^-1 Q_m of the printed consistency term carry no
+    fourth-order Hermite content: their projection on
+    H_xxyy(e) = (e_x^2 - 1/3)(e_y^2 - 1/3) is zero, as for the second-order
+    tensor of R_add the term produces.  This fixes the epsilon entry (minus
+    the e entry), which drops out of the momentum flux."""
+    Fx, Fy = rng.uniform(-0.3, 0.3, (2, 25))
+    q = lbm.from_moments(lbm.consistency_moments(Fx, Fy))
+    hxxyy = (lbm.CX ** 2 - 1 / 3) * (lbm.CY ** 2 - 1 / 3)
+    np.testing.assert_allclose(np.tensordot(hxxyy, q, axes=(0, 0)), 0.0, atol=1e-16)
+    assert np.max(np.abs(q)) > 1e-3  # and the term itself is not zero
+
+
+def test_eos_slope_is_derivative_of_pressure(co):
+    """d p_LBE / d rho returned by eos is the exact derivative of p_LBE
+    (complex step), from the gas to beyond the liquid density."""
+    rho = np.linspace(0.5 * co.rho_g, 1.2 * co.rho_l, 41)
+    p_lbe, dp_lbe, _ = lbm.eos(rho, co)
+    exact = cstep(lambda r: lbm.eos(r, co)[0], rho, np.ones_like(rho))
+    np.testing.assert_allclose(dp_lbe, exact, rtol=1e-13, atol=1e-15)
+
+
 # ---------------------------------------------------------------------------
 # Collision matrix and correction matrices (main Eqs. 6, 10-11)
 # ---------------------------------------------------------------------------
