@@ -1,11 +1,14 @@
 // HIP kernels and C-ABI entry points of the self-tuning-EOS D2Q9 library
 // (gfx950).  See include/lbm.h for the contract of every entry point.
 //
-// Data layout: structure of arrays, x fastest, population i at offset
-// i*P with P = plane_elems (nx*ny rounded up to 64 plus a pad, so that the
-// planes do not start at one offset modulo a large power of two); the
-// caller's plain arrays use P = nx*ny.  Two caller-owned buffers A and B
-// alternate; the buffer that is
+// Data layout, x fastest.  State buffers (state_layout): FP32 states
+// interleave rows, population i of node (x, y) at element (9 y + i) nx + x,
+// when every byte offset fits 32 bits; otherwise, and for the 2-byte
+// storages, nine planes, population i at i*P with P = plane_elems (nx*ny
+// rounded up to 64 plus a pad, so that the planes do not start at one
+// offset modulo a large power of two).  The adjoint state holds planes; the
+// caller's plain arrays hold planes with P = nx*ny.  Two caller-owned
+// buffers A and B alternate; the buffer that is
 // read by the next step holds the post-collision populations of the previous
 // step at their source node ("pull" streaming: f_i(x, t) = src_i(x - e_i)).
 //
@@ -103,7 +106,7 @@ __device__ __forceinline__ int wrap(int i, int n) {
   return i;
 }
 
-// Row offsets (row * nx * ES) of rows y, y-1, y+1 and column offsets
+// Row offsets (row * rp * ES, rp the row pitch) of rows y, y-1, y+1 and column offsets
 // (x * ES) of columns x, x-1, x+1 of a node, periodic.
 template <int ES>
 struct NodeAddr {
@@ -113,8 +116,8 @@ struct NodeAddr {
 // One multiplication per node; the neighbours' offsets are the node's plus
 // or minus one row (column), or the opposite edge.
 template <int ES>
-__device__ __forceinline__ NodeAddr<ES> node_addr(int x, int y, int nx, int ny) {
-  const unsigned rb = ES * (unsigned)nx, r0 = rb * (unsigned)y, rlast = rb * (unsigned)(ny - 1);
+__device__ __forceinline__ NodeAddr<ES> node_addr(int x, int y, int nx, int ny, unsigned rp) {
+  const unsigned rb = ES * rp, r0 = rb * (unsigned)y, rlast = rb * (unsigned)(ny - 1);
   const unsigned c0 = ES * (unsigned)x, clast = ES * (unsigned)(nx - 1);
   return {r0, y == 0 ? rlast : r0 - rb, y == ny - 1 ? 0u : r0 + rb,
           c0, x == 0 ? clast : c0 - ES, x == nx - 1 ? 0u : c0 + ES};
@@ -162,6 +165,26 @@ __device__ __forceinline__ OutPlanes<E> out_planes(void* dst, size_t N) {
 #endif
 __host__ __device__ __forceinline__ size_t plane_elems(int nx, int ny, int es) {
   return ((size_t)nx * ny + 63) / 64 * 64 + (size_t)(LBM_PLANE_PAD / es);
+}
+
+// Layout of a state buffer (A/B, checkpoint): elements from one population
+// to the next (ps) and from one lattice row to the next (rp).  FP32 states
+// interleave rows -- the nine populations of a lattice row are nine
+// consecutive buffer rows, population i of node (x, y) at (9 y + i) nx + x
+// -- when every byte offset fits the 32-bit lane offsets (36 nx ny < 2^32).
+// A wave's nine loads (stores) of a row segment then fall within 9 nx
+// elements instead of nine planes apart, which keeps more of them in open
+// DRAM pages (a data-movement kernel with the step's access pattern moves
+// 3-5 % more bytes per second at 4096^2).  Larger FP32 lattices and the
+// 2-byte storages keep nine planes (ps = plane_elems, rp = nx).
+struct Layout {
+  size_t ps;    // elements between populations
+  unsigned rp;  // elements between lattice rows
+};
+__host__ __device__ __forceinline__ Layout state_layout(int nx, int ny, int es) {
+  if (es == 4 && 36ull * (unsigned long long)nx * (unsigned long long)ny <= 0xFFFFFFFFull)
+    return {(size_t)nx, 9u * (unsigned)nx};
+  return {plane_elems(nx, ny, es), (unsigned)nx};
 }
 
 // Raw stored values arriving at a node: raw_i = src_i(x - e_i).
@@ -311,7 +334,7 @@ __device__ __forceinline__ void issue_tile(const Planes<typename St::E>& P, cons
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * S::TX + tx;
   if constexpr (kInterior) {
     using E = typename St::E;
-    const unsigned rb = St::ES * (unsigned)nx;
+    const unsigned rb = St::ES * state_layout(nx, ny, St::ES).rp;
     Planes<E> Q;  // Q_i + offset(x) = P_i + offset(x - e_i)
 #pragma unroll
     for (int i = 0; i < 9; ++i) Q.p[i] = P.p[i] - (ptrdiff_t)kCy[i] * rb - kCx[i] * St::ES;
@@ -338,14 +361,14 @@ __device__ __forceinline__ void issue_tile(const Planes<typename St::E>& P, cons
     int hx, hy;
     ring_slot<S>(tid, hx, hy);
     const int gx = wrap(x0 + hx - 1, nx), gy = wrap(y0 + hy - 1, ny);
-    pull_raw<typename St::E>(P, node_addr<St::ES>(gx, gy, nx, ny), R.rraw);
+    pull_raw<typename St::E>(P, node_addr<St::ES>(gx, gy, nx, ny, state_layout(nx, ny, St::ES).rp), R.rraw);
     if constexpr (St::kRef) R.rrref = rho_ref[(size_t)gy * nx + gx];
   }
   const int xw = wrap(x0 + tx, nx);
 #pragma unroll
   for (int k = 0; k < S::NPT; ++k) {
     const int yw = wrap(y0 + ty + k * S::WY, ny);
-    pull_raw<typename St::E>(P, node_addr<St::ES>(xw, yw, nx, ny), R.raw[k]);
+    pull_raw<typename St::E>(P, node_addr<St::ES>(xw, yw, nx, ny, state_layout(nx, ny, St::ES).rp), R.raw[k]);
     if constexpr (St::kRef) R.rref[k] = rho_ref[(size_t)yw * nx + xw];
   }
 }
@@ -408,7 +431,8 @@ __global__ __launch_bounds__(S::NTHREADS) void step_kernel(const void* __restric
   using E = typename St::E;
   __shared__ float srho[S::LDS];
   __shared__ float sref[St::kRef ? 3 * S::LDS : 1];
-  const size_t N = plane_elems(nx, ny, St::ES);
+  const Layout L = state_layout(nx, ny, St::ES);
+  const size_t N = L.ps;
   int tx, ty;
   strip_tile(xcd_tile(blockIdx.x, ntiles), ntx, ntiles / ntx, strip, tx, ty);
   const int x0 = tx * S::TX, y0 = ty * S::TY;
@@ -426,7 +450,7 @@ __global__ __launch_bounds__(S::NTHREADS) void step_kernel(const void* __restric
   const int x = x0 + threadIdx.x;
   if (x >= nx) return;
   const OutPlanes<E> Q = out_planes<E>(dst, N);
-  const unsigned rb = St::ES * (unsigned)nx;
+  const unsigned rb = St::ES * L.rp;  // also the row pitch of the 2-byte reference planes (rp = nx)
   const unsigned o0 = rb * (unsigned)(y0 + threadIdx.y) + St::ES * (unsigned)x;
 #pragma unroll
   for (int k = 0; k < S::NPT; ++k) {
@@ -465,7 +489,7 @@ __global__ __launch_bounds__(MomTile::NTHREADS) void moments_kernel(
   using S = MomTile;
   __shared__ float srho[S::LDS];
   __shared__ double sred[3][S::NTHREADS];
-  const size_t N = plane_elems(nx, ny, St::ES);
+  const size_t N = state_layout(nx, ny, St::ES).ps;
   const int x0 = (blockIdx.x % ntx) * S::TX, y0 = (blockIdx.x / ntx) * S::TY;
   float f[S::NPT][9];
   float rho[S::NPT];
@@ -535,7 +559,7 @@ template <class St>
 __device__ __forceinline__ void put_node(int x, int y, int nx, int ny, const float* f, const RefPoly<float>& q,
                                          void* dst, uint16_t* ref_out) {
   using E = typename St::E;
-  const size_t P = plane_elems(nx, ny, St::ES);
+  const Layout L = state_layout(nx, ny, St::ES);
   float rd[9];
   if constexpr (St::kRef) {
     const float r = ref_density(density(f));
@@ -549,7 +573,7 @@ __device__ __forceinline__ void put_node(int x, int y, int nx, int ny, const flo
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const int xs = wrap(x - kCx[i], nx), ys = wrap(y - kCy[i], ny);
-    d[(size_t)i * P + (size_t)ys * nx + xs] = out[i];
+    d[(size_t)i * L.ps + (size_t)ys * L.rp + xs] = out[i];
   }
 }
 
@@ -596,7 +620,8 @@ __global__ __launch_bounds__(BLK) void get_state_kernel(const void* __restrict__
   if (o >= N) return;
   const int x = (int)(o % nx), y = (int)(o / nx);
   E raw[9];
-  pull_raw<E>(planes<E>(src, plane_elems(nx, ny, St::ES)), node_addr<St::ES>(x, y, nx, ny), raw);
+  const Layout L = state_layout(nx, ny, St::ES);
+  pull_raw<E>(planes<E>(src, L.ps), node_addr<St::ES>(x, y, nx, ny, L.rp), raw);
   float f[9];
   decode<St>(raw, St::kRef ? ref_in[o] : 0, q, f);
 #pragma unroll
@@ -730,7 +755,7 @@ template <class S, bool kInterior>
 __device__ __forceinline__ void adjoint_tile(const float* __restrict__ fsrc, const float* __restrict__ adj_in,
                                              float* __restrict__ adj_out, int nx, int ny, int x0, int y0,
                                              const Coef<float>& c, float* srho, float* snu, float* sa, float* th) {
-  const size_t N = plane_elems(nx, ny, 4);  // state and adjoint planes alike
+  const size_t N = plane_elems(nx, ny, 4);  // adjoint planes
   const Planes<float> P = planes<float>(adj_in, N);
   const unsigned rb = 4u * (unsigned)nx;
   const int x = x0 + threadIdx.x;
@@ -741,7 +766,7 @@ __device__ __forceinline__ void adjoint_tile(const float* __restrict__ fsrc, con
   AHalo<S> h;
   {
     TileRegs<S, StoreF32> R;
-    issue_tile<S, StoreF32, kInterior>(planes<float>(fsrc, N), nullptr, nx, ny, x0, y0, R);
+    issue_tile<S, StoreF32, kInterior>(planes<float>(fsrc, state_layout(nx, ny, 4).ps), nullptr, nx, ny, x0, y0, R);
     load_a<S, kInterior>(adj_in + 9 * N, adj_in + 10 * N, nx, ny, x0, y0, h);
     // lam-bar_i(y) = L_i(y + e_i) (+ nu(y + e_i) below)
 #pragma unroll
@@ -753,7 +778,7 @@ __device__ __forceinline__ void adjoint_tile(const float* __restrict__ fsrc, con
 #pragma unroll
         for (int i = 0; i < 9; ++i) lb[k][i] = ldb<float>(P.p[i] + (ptrdiff_t)kCy[i] * rb + kCx[i] * 4, o);
       } else {
-        const NodeAddr<4> a = node_addr<4>(x, y, nx, ny);
+        const NodeAddr<4> a = node_addr<4>(x, y, nx, ny, (unsigned)nx);
         lb[k][0] = ldb<float>(P.p[0], a.r0 + a.c0);
         lb[k][1] = ldb<float>(P.p[1], a.r0 + a.cp);
         lb[k][2] = ldb<float>(P.p[2], a.rp + a.c0);

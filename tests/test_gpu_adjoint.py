@@ -22,7 +22,7 @@ import workloads as wl
 from oracle import adjoint as adj
 from oracle import hostmap as hm
 from oracle import lbm
-from tests._gpu_helpers import oracle_init, params_pair, planes_of
+from tests._gpu_helpers import fp32_state_of, oracle_init, params_pair, planes_of
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -53,11 +53,13 @@ def param_term_scale(f, lam, co):
     return np.array(out)
 
 
-@pytest.fixture(scope="module", params=[(40, 30), (200, 35)], ids=["40x30", "200x35"])
+@pytest.fixture(scope="module", params=[(40, 30), (200, 35), (320, 35)], ids=["40x30", "200x35", "320x35"])
 def case(request):
-    """A small lattice (every tile touches the periodic edge), and one with
-    interior adjoint tiles next to ragged edges in both directions.  Sides
-    are multiples of 5 for the oracle's colouring."""
+    """A small lattice (every tile touches the periodic edge), one with
+    interior adjoint tiles next to ragged edges in both directions, and one
+    whose width is a multiple of 64 (interior tiles then read the forward
+    state through the run-relative addressing).  Sides are multiples of 5
+    for the oracle's colouring."""
     nx, ny = request.param
     _, co = params_pair(nx, ny, tr=0.7, width=5.0)
     f = nonequilibrium_state(nx, ny, co, 5)
@@ -136,7 +138,7 @@ def test_step_saved_is_bitwise_lbm_step():
         lat.step_saved(bufs[k % 2], bufs[(k + 1) % 2])
     lat.step(5)
     lat.save_state(bufs[2])
-    assert torch.equal(planes_of(bufs[1], nx, ny, 9), planes_of(bufs[2], nx, ny, 9))
+    assert torch.equal(fp32_state_of(bufs[1], nx, ny), fp32_state_of(bufs[2], nx, ny))
 
 
 def test_native_segment_calls_match_single_steps():
@@ -151,7 +153,7 @@ def test_native_segment_calls_match_single_steps():
     single = [chain[0]] + [lat.checkpoint_buffer() for _ in range(n)]
     for j in range(n):
         lat.step_saved(single[j], single[j + 1])
-    assert all(torch.equal(planes_of(a, nx, ny, 9), planes_of(b, nx, ny, 9)) for a, b in zip(chain, single))
+    assert all(torch.equal(fp32_state_of(a, nx, ny), fp32_state_of(b, nx, ny)) for a, b in zip(chain, single))
     lam = np.random.default_rng(3).standard_normal((9, ny, nx))
     a, b = lat.adjoint_seed(lam), lat.adjoint_buffer()
     lat.adjoint_theta(reset=True)

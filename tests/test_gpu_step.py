@@ -48,12 +48,15 @@ def test_set_get_state_roundtrip_is_exact():
 
 
 @pytest.mark.parametrize("nx,ny,steps", [(70, 37, 40), (64, 16, 25), (129, 17, 10), (5, 200, 20), (772, 37, 40),
-                                         (1300, 410, 10)])
+                                         (1300, 410, 10), (1024, 256, 10), (1024, 512, 6)])
 def test_step_parity_ragged(nx, ny, steps):
     """Several tiles and a ragged tail in both directions; 772 x 37 also has
     interior tiles (the fast addressing path) next to edge tiles.  Lattices
     with fewer 256 x 8 tiles than CUs run smaller tiles; 1300 x 410 (312
-    tiles) runs the 256 x 8 tiles of the large workloads, with ragged tails."""
+    tiles) runs the 256 x 8 tiles of the large workloads, with ragged tails.
+    Widths that are multiples of 64 address the FP32 state relative to the
+    tile's run: 1024 x 256 with the 128 x 8 tiles, 1024 x 512 with the
+    256 x 8 tiles (256 of them)."""
     co, rho, ux, uy = droplet_case(nx, ny, seed=nx)
     lat = lattice(nx, ny, rho, ux, uy, tr=0.8)
     f = oracle_init(co, rho, ux, uy)
