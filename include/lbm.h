@@ -206,16 +206,17 @@ int lbm_step_saved_chain(lbm_ctx* ctx, void* const* bufs, int32_t n);
  * theta = (G'^2, K', R T).
  *
  * Adjoint states live in caller-owned device buffers of lbm_adjoint_bytes
- * (eleven FP32 planes in an internal layout: Lambda is held as nine
- * planes plus the two-component adjoint of the force-stencil gradient, which
- * the next step scatters to the neighbour densities).  lbm_adjoint_seed and
+ * (eleven FP32 fields in an internal layout: Lambda is held as nine fields
+ * plus the two-component adjoint of the force-stencil gradient, which the
+ * next step scatters to the neighbour densities; rows interleaved when
+ * 44*nx*ny < 2^32, else eleven planes).  lbm_adjoint_seed and
  * lbm_adjoint_get convert from and to plain Lambda arrays in the SoA layout
  * of the populations.  The accumulator starts at zero when the context is
  * created and is summed and cleared by lbm_adjoint_theta.  Accumulation and
  * its sum run in a fixed order: repeated runs give identical bits. */
 
 /* Bytes of one adjoint state buffer (11*P*4, P as for lbm_state_bytes with
- * FP32 planes); 0 for the 2-byte storages or on error. */
+ * FP32 elements); 0 for the 2-byte storages or on error. */
 size_t lbm_adjoint_bytes(const lbm_params* p);
 
 /* adj := the adjoint state of Lambda = lam (device float, 9*nx*ny). */

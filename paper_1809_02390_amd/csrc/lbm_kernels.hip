@@ -187,6 +187,15 @@ __host__ __device__ __forceinline__ Layout state_layout(int nx, int ny, int es) 
   return {plane_elems(nx, ny, es), (unsigned)nx};
 }
 
+// Layout of an adjoint state buffer: eleven fields (L_0..L_8, A_x, A_y)
+// with rows interleaved like the FP32 state when every byte offset fits 32
+// bits (44 nx ny < 2^32), else eleven planes plane_elems apart.
+__host__ __device__ __forceinline__ Layout adj_layout(int nx, int ny) {
+  if (44ull * (unsigned long long)nx * (unsigned long long)ny <= 0xFFFFFFFFull)
+    return {(size_t)nx, 11u * (unsigned)nx};
+  return {plane_elems(nx, ny, 4), (unsigned)nx};
+}
+
 // Raw stored values arriving at a node: raw_i = src_i(x - e_i).
 template <typename E>
 __device__ __forceinline__ void pull_raw(const Planes<E>& P, const NodeAddr<sizeof(E)>& a, E* r) {
@@ -668,7 +677,7 @@ struct AHalo {
 
 template <class S, bool kInterior = false>
 __device__ __forceinline__ void load_a(const float* __restrict__ ax, const float* __restrict__ ay, int nx, int ny,
-                                       int x0, int y0, AHalo<S>& h) {
+                                       unsigned rp, int x0, int y0, AHalo<S>& h) {
   using L = AdjLds<S>;
   const int tid = threadIdx.y * S::TX + threadIdx.x;
 #pragma unroll
@@ -676,8 +685,8 @@ __device__ __forceinline__ void load_a(const float* __restrict__ ax, const float
     const int p = tid + r * S::NTHREADS;
     if (p >= L::NA) break;
     const int hx = p % L::AW, hy = p / L::AW;
-    const size_t o = kInterior ? (size_t)(y0 + hy - 2) * nx + (x0 + hx - 2)
-                               : (size_t)wrap(y0 + hy - 2, ny) * nx + wrap(x0 + hx - 2, nx);
+    const size_t o = kInterior ? (size_t)(y0 + hy - 2) * rp + (x0 + hx - 2)
+                               : (size_t)wrap(y0 + hy - 2, ny) * rp + wrap(x0 + hx - 2, nx);
     h.v[r][0] = ax[o];
     h.v[r][1] = ay[o];
   }
@@ -716,9 +725,9 @@ __device__ __forceinline__ void put_nu(const AHalo<S>& h, float* sa, float* snu)
 // nu of the tile plus a one-node ring from the A planes (load_a, put_nu).
 template <class S, bool kInterior = false>
 __device__ __forceinline__ void stage_nu(const float* __restrict__ ax, const float* __restrict__ ay, int nx, int ny,
-                                         int x0, int y0, float* sa, float* snu) {
+                                         unsigned rp, int x0, int y0, float* sa, float* snu) {
   AHalo<S> h;
-  load_a<S, kInterior>(ax, ay, nx, ny, x0, y0, h);
+  load_a<S, kInterior>(ax, ay, nx, ny, rp, x0, y0, h);
   put_nu<S>(h, sa, snu);
 }
 
@@ -755,9 +764,10 @@ template <class S, bool kInterior>
 __device__ __forceinline__ void adjoint_tile(const float* __restrict__ fsrc, const float* __restrict__ adj_in,
                                              float* __restrict__ adj_out, int nx, int ny, int x0, int y0,
                                              const Coef<float>& c, float* srho, float* snu, float* sa, float* th) {
-  const size_t N = plane_elems(nx, ny, 4);  // adjoint planes
+  const Layout A = adj_layout(nx, ny);
+  const size_t N = A.ps;
   const Planes<float> P = planes<float>(adj_in, N);
-  const unsigned rb = 4u * (unsigned)nx;
+  const unsigned rb = 4u * A.rp;
   const int x = x0 + threadIdx.x;
   const unsigned o0 = rb * (unsigned)(y0 + threadIdx.y) + 4u * (unsigned)x;
   float f[S::NPT][9];
@@ -767,7 +777,7 @@ __device__ __forceinline__ void adjoint_tile(const float* __restrict__ fsrc, con
   {
     TileRegs<S, StoreF32> R;
     issue_tile<S, StoreF32, kInterior>(planes<float>(fsrc, state_layout(nx, ny, 4).ps), nullptr, nx, ny, x0, y0, R);
-    load_a<S, kInterior>(adj_in + 9 * N, adj_in + 10 * N, nx, ny, x0, y0, h);
+    load_a<S, kInterior>(adj_in + 9 * N, adj_in + 10 * N, nx, ny, A.rp, x0, y0, h);
     // lam-bar_i(y) = L_i(y + e_i) (+ nu(y + e_i) below)
 #pragma unroll
     for (int k = 0; k < S::NPT; ++k) {
@@ -778,7 +788,7 @@ __device__ __forceinline__ void adjoint_tile(const float* __restrict__ fsrc, con
 #pragma unroll
         for (int i = 0; i < 9; ++i) lb[k][i] = ldb<float>(P.p[i] + (ptrdiff_t)kCy[i] * rb + kCx[i] * 4, o);
       } else {
-        const NodeAddr<4> a = node_addr<4>(x, y, nx, ny, (unsigned)nx);
+        const NodeAddr<4> a = node_addr<4>(x, y, nx, ny, A.rp);
         lb[k][0] = ldb<float>(P.p[0], a.r0 + a.c0);
         lb[k][1] = ldb<float>(P.p[1], a.r0 + a.cp);
         lb[k][2] = ldb<float>(P.p[2], a.rp + a.c0);
@@ -848,9 +858,10 @@ __global__ __launch_bounds__(S::NTHREADS) void adjoint_finish_kernel(
   using L = AdjLds<S>;
   __shared__ float snu[S::LDS];
   __shared__ __align__(8) float sa[L::NSA];
-  const size_t N = (size_t)nx * ny, P = plane_elems(nx, ny, 4);
+  const size_t N = (size_t)nx * ny;
+  const Layout A = adj_layout(nx, ny);
   const int x0 = (blockIdx.x % ntx) * S::TX, y0 = (blockIdx.x / ntx) * S::TY;
-  stage_nu<S>(adj + 9 * P, adj + 10 * P, nx, ny, x0, y0, sa, snu);
+  stage_nu<S>(adj + 9 * A.ps, adj + 10 * A.ps, nx, ny, A.rp, x0, y0, sa, snu);
   float th[3] = {0.0f, 0.0f, 0.0f};
   const int x = x0 + threadIdx.x;
 #pragma unroll
@@ -858,10 +869,10 @@ __global__ __launch_bounds__(S::NTHREADS) void adjoint_finish_kernel(
     const int ly = threadIdx.y + k * S::WY, y = y0 + ly;
     if (x >= nx || y >= ny) break;
     const float nu = snu[(ly + 1) * S::LW + threadIdx.x + 1];
-    const size_t o = (size_t)y * nx + x;
+    const size_t o = (size_t)y * nx + x, oa = (size_t)y * A.rp + x;
     float lam[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) lam[i] = adj[(size_t)i * P + o] + nu;
+    for (int i = 0; i < 9; ++i) lam[i] = adj[(size_t)i * A.ps + oa] + nu;
     if constexpr (kInit) {
       out[o] = equilibrium_vjp<float>(rho0[o], ux0 ? ux0[o] : 0.0f, uy0 ? uy0[o] : 0.0f, c, lam, th);
     } else {
@@ -872,16 +883,19 @@ __global__ __launch_bounds__(S::NTHREADS) void adjoint_finish_kernel(
   if constexpr (kInit) block_accumulate<S>(th, reinterpret_cast<double*>(sa), partials);
 }
 
-// Adjoint state (planes P elements apart) from a plain Lambda (planes N
-// apart): L = lam, A = 0.
+// Adjoint state (adj_layout) from a plain Lambda (planes nx*ny apart):
+// L = lam, A = 0.
 __global__ __launch_bounds__(BLK) void adjoint_seed_kernel(const float* __restrict__ lam, float* __restrict__ adj,
-                                                          size_t N, size_t P) {
+                                                          int nx, int ny) {
+  const size_t N = (size_t)nx * ny;
   const size_t o = (size_t)blockIdx.x * BLK + threadIdx.x;
   if (o >= N) return;
+  const Layout A = adj_layout(nx, ny);
+  const size_t oa = o / nx * A.rp + o % nx;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) adj[(size_t)i * P + o] = lam[(size_t)i * N + o];
-  adj[9 * P + o] = 0.0f;
-  adj[10 * P + o] = 0.0f;
+  for (int i = 0; i < 9; ++i) adj[(size_t)i * A.ps + oa] = lam[(size_t)i * N + o];
+  adj[9 * A.ps + oa] = 0.0f;
+  adj[10 * A.ps + oa] = 0.0f;
 }
 
 // ---------------------------------------------------------------------------
@@ -1368,8 +1382,7 @@ int lbm_adjoint_seed(lbm_ctx* ctx, const float* lam, void* adj) {
   if (!lam || !adj) return fail(LBM_EINVAL, "lam and adj must be device buffers");
   if (int st = set_device(ctx)) return st;
   const size_t N = (size_t)ctx->p.nx * ctx->p.ny;
-  adjoint_seed_kernel<<<grid1(N), BLK, 0, ctx->stream>>>(lam, static_cast<float*>(adj), N,
-                                                        plane_elems(ctx->p.nx, ctx->p.ny, 4));
+  adjoint_seed_kernel<<<grid1(N), BLK, 0, ctx->stream>>>(lam, static_cast<float*>(adj), ctx->p.nx, ctx->p.ny);
   HIP_OK(hipGetLastError());
   return LBM_OK;
 }

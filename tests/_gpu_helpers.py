@@ -76,6 +76,16 @@ def fp32_state_of(buf, nx, ny):
     return planes_of(buf, nx, ny, 9)
 
 
+def adj_state_of(buf, nx, ny):
+    """The eleven fields (11, ny*nx) of an adjoint state buffer (L_0..L_8,
+    A_x, A_y): rows interleaved (field i of node (x, y) at element
+    (11 y + i) nx + x) when 44 nx ny < 2^32, else eleven padded planes."""
+    n = nx * ny
+    if 44 * n <= 0xFFFFFFFF:
+        return buf[: 11 * n * 4].view(torch.float32).view(ny, 11, nx).permute(1, 0, 2).reshape(11, n)
+    return planes_of(buf, nx, ny, 11)
+
+
 def planes_of(buf, nx, ny, nplanes, es=4):
     """The nplanes data regions (nplanes, ny*nx) of an internal byte buffer
     in plane layout (adjoint state, 2-byte state): planes P elements apart,

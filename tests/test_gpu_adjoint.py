@@ -22,7 +22,7 @@ import workloads as wl
 from oracle import adjoint as adj
 from oracle import hostmap as hm
 from oracle import lbm
-from tests._gpu_helpers import fp32_state_of, oracle_init, params_pair, planes_of
+from tests._gpu_helpers import adj_state_of, fp32_state_of, oracle_init, params_pair
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -164,7 +164,7 @@ def test_native_segment_calls_match_single_steps():
         lat.adjoint_step(chain[j], x, y)
         x, y = y, x
     th_single = lat.adjoint_theta(reset=True)
-    assert out is b and torch.equal(planes_of(out, nx, ny, 11), planes_of(x, nx, ny, 11)) and th_run == th_single
+    assert out is b and torch.equal(adj_state_of(out, nx, ny), adj_state_of(x, nx, ny)) and th_run == th_single
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
