@@ -1,13 +1,13 @@
 // HIP kernels and C-ABI entry points of the self-tuning-EOS D2Q9 library
 // (gfx950).  See include/lbm.h for the contract of every entry point.
 //
-// Data layout, x fastest.  State buffers (state_layout): FP32 states
-// interleave rows, population i of node (x, y) at element (9 y + i) nx + x,
-// when every byte offset fits 32 bits; otherwise, and for the 2-byte
-// storages, nine planes, population i at i*P with P = plane_elems (nx*ny
-// rounded up to 64 plus a pad, so that the planes do not start at one
-// offset modulo a large power of two).  The adjoint state holds planes; the
-// caller's plain arrays hold planes with P = nx*ny.  Two caller-owned
+// Data layout, x fastest.  State buffers (state_layout) interleave rows,
+// population i of node (x, y) at element (9 y + i) nx + x, when every byte
+// offset fits 32 bits; otherwise they hold nine planes, population i at
+// i*P with P = plane_elems (nx*ny rounded up to 64 plus a pad, so that the
+// planes do not start at one offset modulo a large power of two).  The
+// adjoint state does the same with eleven fields (adj_layout); the 2-byte
+// reference densities and the caller's plain arrays hold planes of nx*ny.  Two caller-owned
 // buffers A and B alternate; the buffer that is
 // read by the next step holds the post-collision populations of the previous
 // step at their source node ("pull" streaming: f_i(x, t) = src_i(x - e_i)).
@@ -168,21 +168,22 @@ __host__ __device__ __forceinline__ size_t plane_elems(int nx, int ny, int es) {
 }
 
 // Layout of a state buffer (A/B, checkpoint): elements from one population
-// to the next (ps) and from one lattice row to the next (rp).  FP32 states
+// to the next (ps) and from one lattice row to the next (rp).  States
 // interleave rows -- the nine populations of a lattice row are nine
 // consecutive buffer rows, population i of node (x, y) at (9 y + i) nx + x
-// -- when every byte offset fits the 32-bit lane offsets (36 nx ny < 2^32).
+// -- when every byte offset fits the 32-bit lane offsets (9 es nx ny < 2^32).
 // A wave's nine loads (stores) of a row segment then fall within 9 nx
 // elements instead of nine planes apart, which keeps more of them in open
 // DRAM pages (a data-movement kernel with the step's access pattern moves
-// 3-5 % more bytes per second at 4096^2).  Larger FP32 lattices and the
-// 2-byte storages keep nine planes (ps = plane_elems, rp = nx).
+// 3-5 % more bytes per second at 4096^2; the FP32 step gains 7 %, the
+// 2-byte steps 1 %).  Larger lattices keep nine planes (ps = plane_elems,
+// rp = nx).
 struct Layout {
   size_t ps;    // elements between populations
   unsigned rp;  // elements between lattice rows
 };
 __host__ __device__ __forceinline__ Layout state_layout(int nx, int ny, int es) {
-  if (es == 4 && 36ull * (unsigned long long)nx * (unsigned long long)ny <= 0xFFFFFFFFull)
+  if (9ull * es * (unsigned long long)nx * (unsigned long long)ny <= 0xFFFFFFFFull)
     return {(size_t)nx, 9u * (unsigned)nx};
   return {plane_elems(nx, ny, es), (unsigned)nx};
 }
@@ -347,14 +348,14 @@ __device__ __forceinline__ void issue_tile(const Planes<typename St::E>& P, cons
     Planes<E> Q;  // Q_i + offset(x) = P_i + offset(x - e_i)
 #pragma unroll
     for (int i = 0; i < 9; ++i) Q.p[i] = P.p[i] - (ptrdiff_t)kCy[i] * rb - kCx[i] * St::ES;
-    const char* rref = reinterpret_cast<const char*>(rho_ref);  // 2-byte plane: same offsets as ES = 2
+    const char* rref = reinterpret_cast<const char*>(rho_ref);  // reference plane, row pitch 2 nx bytes
     if (tid < S::NRING) {
       int hx, hy;
       ring_slot<S>(tid, hx, hy);
       const unsigned off = (unsigned)(y0 + hy - 1) * rb + (unsigned)(x0 + hx - 1) * St::ES;
 #pragma unroll
       for (int i = 0; i < 9; ++i) R.rraw[i] = ldb<E>(Q.p[i], off);
-      if constexpr (St::kRef) R.rrref = ldb<uint16_t>(rref, off);
+      if constexpr (St::kRef) R.rrref = ldb<uint16_t>(rref, 2u * ((unsigned)(y0 + hy - 1) * nx + (unsigned)(x0 + hx - 1)));
     }
     const unsigned off0 = (unsigned)(y0 + ty) * rb + (unsigned)(x0 + tx) * St::ES;
 #pragma unroll
@@ -362,7 +363,7 @@ __device__ __forceinline__ void issue_tile(const Planes<typename St::E>& P, cons
       const unsigned off = off0 + (unsigned)(k * S::WY) * rb;
 #pragma unroll
       for (int i = 0; i < 9; ++i) R.raw[k][i] = ldb<E>(Q.p[i], off);
-      if constexpr (St::kRef) R.rref[k] = ldb<uint16_t>(rref, off);
+      if constexpr (St::kRef) R.rref[k] = ldb<uint16_t>(rref, 2u * ((unsigned)(y0 + ty + k * S::WY) * nx + (unsigned)(x0 + tx)));
     }
     return;
   }
@@ -482,7 +483,7 @@ __global__ __launch_bounds__(S::NTHREADS) void step_kernel(const void* __restric
       for (int i = 0; i < 9; ++i) out[i] = f[k][i];
     }
     const unsigned o = o0 + (unsigned)(k * S::WY) * rb;
-    if constexpr (St::kRef) *reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(ref_out) + o) = f32_to_f16(nb[0]);
+    if constexpr (St::kRef) ref_out[(size_t)y * nx + x] = f32_to_f16(nb[0]);
 #pragma unroll
     for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(out[i], reinterpret_cast<E*>(Q.p[i] + o));
   }
