@@ -19,7 +19,7 @@ the forward's) and the adjoint steps run back through them
     dL/d(sigma, W, T_r) = J^T dL/d theta,   J = lbm_param_jacobian.
 
 Device memory: ceil(n / every) + 1 checkpoints + (every - 1) segment states
-+ two adjoint states (11 planes each), all FP32 over nx*ny nodes.  With
++ two adjoint states (11 fields each), all FP32 over nx*ny nodes.  With
 every = 1 every state is kept and nothing is recomputed (the forward +
 adjoint then moves 72 + 124 instead of 72 + 72 + 124 bytes per node and
 step; at 2048^2 x 1000 steps that is 151 GB of checkpoints, which HBM3E

@@ -88,7 +88,8 @@ def adj_state_of(buf, nx, ny):
 
 def planes_of(buf, nx, ny, nplanes, es=4):
     """The nplanes data regions (nplanes, ny*nx) of an internal byte buffer
-    in plane layout (adjoint state, 2-byte state): planes P elements apart,
+    in plane layout (states and adjoint states of lattices too large for
+    interleaved rows): planes P elements apart,
     with P = nx*ny rounded up to 64 plus 16640 bytes' worth of elements
     (include/lbm.h); the padding between planes holds no data."""
     p = -(-nx * ny // 64) * 64 + 16640 // es

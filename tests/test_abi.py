@@ -69,8 +69,8 @@ def test_invalid_parameters_rejected(bad):
 
 
 def plane(nx, ny, es):
-    """Elements between planes of an internal buffer: nx*ny rounded up to 64
-    plus a 16640-byte pad (include/lbm.h)."""
+    """P of the internal buffer sizes (9 P or 11 P elements): nx*ny rounded
+    up to 64 plus a 16640-byte pad (include/lbm.h)."""
     return -(-nx * ny // 64) * 64 + 16640 // es
 
 

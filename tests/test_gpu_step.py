@@ -256,7 +256,8 @@ def test_sampled_parity_coalescence_16384x8192():
 
 def test_sampled_parity_largest_lattice():
     """The largest lattice the library accepts, 16384 x 14563 (9 nx ny just
-    below 2^31; byte offsets inside a plane up to 0.95 GB): the spinodal
+    below 2^31; its FP32 state too large for interleaved rows, so nine
+    planes with byte offsets inside a plane up to 0.95 GB): the spinodal
     field (T_r = 0.7, mean of the coexistence densities +- 0.01, seed 3),
     5 steps, sampled nodes against oracle light-cone crops, including the
     last row and column."""
