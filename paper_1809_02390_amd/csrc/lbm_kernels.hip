@@ -336,8 +336,8 @@ __device__ __forceinline__ bool interior_tile(int x0, int y0, int nx, int ny) {
 }
 
 // Issue the loads of the tile at (x0, y0); ring loads first.  kInterior
-// (interior_tile true): every plane's pull shift goes into its uniform base,
-// so the nine loads of a node share one offset register.
+// (interior_tile true): every population's pull shift goes into its uniform
+// base, so the nine loads of a node share one offset register.
 template <class S, class St, bool kInterior = false>
 __device__ __forceinline__ void issue_tile(const Planes<typename St::E>& P, const uint16_t* __restrict__ rho_ref,
                                            int nx, int ny, int x0, int y0, TileRegs<S, St>& R) {
