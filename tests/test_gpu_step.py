@@ -275,6 +275,29 @@ def test_sampled_parity_largest_lattice():
     assert np.abs(got - ref).max() / co.rho_l <= TOL
 
 
+@pytest.mark.parametrize("ny", [7281, 7282])
+def test_sampled_parity_at_the_row_layout_limit(ny):
+    """FP32 states interleave rows while every byte offset fits 32 bits
+    (36 nx ny < 2^32): 16384 x 7281 is the tallest such lattice of that
+    width (largest offset 4 294 508 540 bytes), 16384 x 7282 the first that
+    falls back to nine planes.  Spinodal field (T_r = 0.7), 5 steps,
+    sampled nodes against oracle crops, including the last row, whose
+    offsets are the largest."""
+    nx, steps = 16384, 5
+    assert (36 * nx * ny < 2 ** 32) == (ny == 7281)
+    _, co = params_pair(nx, ny, tr=0.7, width=10.0)
+    rho = wl.uniform_noise(nx, ny, 0.5 * (co.rho_g + co.rho_l), 0.01, seed=ny)
+    lat = lattice(nx, ny, rho, tr=0.7, width=10.0)
+    lat.step(steps)
+    pts = [(nx - 1, ny - 1), (0, ny - 1), (nx // 2, ny - 2), (0, 0), (nx - 1, 0), (777, ny // 2)]
+    ref = sampled_oracle(co, rho, pts, steps)
+    st = lat.state()
+    got = device_samples(st, pts)
+    del st
+    lat.close()
+    assert np.abs(got - ref).max() / co.rho_l <= TOL
+
+
 def test_two_lattices_on_two_streams_match_single_runs():
     """Every launch goes to its context's stream and contexts share no device
     state: two lattices (FP32 and FP16) stepped in turn on two streams end

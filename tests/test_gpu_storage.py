@@ -170,3 +170,24 @@ def test_sampled_parity_coalescence_16384x8192(storage):
     del st
     lat.close()
     assert np.abs(got - ref).max() / co.rho_l <= STEP_TOL[storage]
+
+
+@pytest.mark.parametrize("storage", STORAGES)
+def test_sampled_parity_largest_lattice(storage):
+    """The largest lattice the library accepts, 16384 x 14563, in 2-byte
+    storage: its state interleaves rows (18 nx ny < 2^32) with byte offsets
+    up to just under 4 GiB.  Spinodal field (T_r = 0.7), 5 steps, sampled
+    nodes against oracle crops, including the last row and column."""
+    nx, ny, steps = 16384, 14563, 5
+    assert 18 * nx * ny < 2 ** 32
+    _, co = params_pair(nx, ny, tr=0.7, width=10.0)
+    rho = wl.uniform_noise(nx, ny, 0.5 * (co.rho_g + co.rho_l), 0.01, seed=3)
+    lat = lattice(nx, ny, rho, tr=0.7, width=10.0, storage=storage)
+    lat.step(steps)
+    pts = [(nx - 1, ny - 1), (0, ny - 1), (nx // 2, ny - 2), (0, 0), (nx // 2, ny // 2), (nx - 3, 9999)]
+    ref = sampled_oracle(co, rho, pts, steps)
+    st = lat.state()
+    got = device_samples(st, pts)
+    del st
+    lat.close()
+    assert np.abs(got - ref).max() / co.rho_l <= STEP_TOL[storage]
