@@ -22,7 +22,7 @@ import workloads as wl
 from oracle import adjoint as adj
 from oracle import hostmap as hm
 from oracle import lbm
-from tests._gpu_helpers import adj_state_of, fp32_state_of, oracle_init, params_pair
+from tests._gpu_helpers import adj_state_of, crop_periodic, fp32_state_of, lattice, oracle_init, params_pair
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -89,6 +89,34 @@ def test_adjoint_step_matches_oracle(case):
     ref_th = adj.step_param_vjp(f, lam, co)
     scale = param_term_scale(f, lam, co)
     assert np.all(np.abs(dth - ref_th) <= 1e-5 * scale), (dth, ref_th, scale)
+
+
+def test_adjoint_step_sampled_spinodal_4096():
+    """One adjoint step on the 4096^2 spinodal workload (T_r = 0.7, W = 10,
+    after 50 forward steps), whose state and adjoint state interleave rows
+    and whose tiles run in strip order: Lambda(t) at sampled nodes, interior
+    and on the periodic edges, against the oracle's exact VJP on a 15 x 15
+    periodic crop of f(t) and Lambda(t+1) around each.  Lambda(t) at a node
+    reads f(t) and Lambda(t+1) within two nodes (streaming and the force
+    stencil), so the crop's seam, seven nodes out, is beyond its reach."""
+    n, half = 4096, 7
+    _, co = params_pair(n, n, tr=0.7, width=10.0)
+    lat = lattice(n, n, wl.spinodal(co, n=n), tr=0.7, width=10.0)
+    lat.step(50)
+    ck = lat.save_state()
+    f = lat.state()
+    gen = torch.Generator(device=DEV).manual_seed(11)
+    lam = torch.randn((9, n, n), generator=gen, device=DEV)
+    a, b = lat.adjoint_seed(lam), lat.adjoint_buffer()
+    lat.adjoint_step(ck, a, b)
+    got_all = lat.adjoint_get(b)
+    for x, y in [(2047, 2048), (0, 0), (n - 1, n - 1), (0, n - 1), (1234, 7), (n - 2, 3000)]:
+        fc = crop_periodic(f, x, y, half).double().cpu().numpy()
+        lc = crop_periodic(lam, x, y, half).double().cpu().numpy()
+        ref = adj.step_vjp(fc, lc, co)[:, half, half]
+        got = got_all[:, y, x].double().cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max(), (x, y, got, ref)
+    lat.close()
 
 
 def test_two_adjoint_steps_match_oracle(case):
