@@ -30,6 +30,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <type_traits>
 
 #include "lbm.h"
 #include "lbm_cell.h"
@@ -116,10 +117,11 @@ struct NodeAddr {
 // One multiplication per node; the neighbours' offsets are the node's plus
 // or minus one row (column), or the opposite edge.
 template <int ES>
-__device__ __forceinline__ NodeAddr<ES> node_addr(int x, int y, int nx, int ny, unsigned rp) {
-  const unsigned rb = ES * rp, r0 = rb * (unsigned)y, rlast = rb * (unsigned)(ny - 1);
+__device__ __forceinline__ NodeAddr<ES> node_addr(int x, int y, int nx, int ny, unsigned rp, int yb = 0) {
+  // rows relative to row yb; with yb > 0 (band addressing) y never wraps
+  const unsigned rb = ES * rp, r0 = rb * (unsigned)(y - yb), rlast = rb * (unsigned)(ny - 1 - yb);
   const unsigned c0 = ES * (unsigned)x, clast = ES * (unsigned)(nx - 1);
-  return {r0, y == 0 ? rlast : r0 - rb, y == ny - 1 ? 0u : r0 + rb,
+  return {r0, y == 0 ? rlast : r0 - rb, y == ny - 1 ? rb * (unsigned)(-yb) : r0 + rb,
           c0, x == 0 ? clast : c0 - ES, x == nx - 1 ? 0u : c0 + ES};
 }
 
@@ -170,23 +172,36 @@ __host__ __device__ __forceinline__ size_t plane_elems(int nx, int ny, int es) {
 // Layout of a state buffer (A/B, checkpoint): elements from one population
 // to the next (ps) and from one lattice row to the next (rp).  States
 // interleave rows -- the nine populations of a lattice row are nine
-// consecutive buffer rows, population i of node (x, y) at (9 y + i) nx + x
-// -- when every byte offset fits the 32-bit lane offsets (9 es nx ny < 2^32).
+// consecutive buffer rows, population i of node (x, y) at (9 y + i) nx + x.
 // A wave's nine loads (stores) of a row segment then fall within 9 nx
 // elements instead of nine planes apart, which keeps more of them in open
 // DRAM pages (a data-movement kernel with the step's access pattern moves
-// 3-5 % more bytes per second at 4096^2; the FP32 step gains 7 %, the
-// 2-byte steps 1 %).  Larger lattices keep nine planes (ps = plane_elems,
-// rp = nx).
+// 3-6 % more bytes per second; the FP32 step gains 7 % at 4096^2, the
+// 2-byte steps 1 %).
 struct Layout {
   size_t ps;    // elements between populations
   unsigned rp;  // elements between lattice rows
 };
-__host__ __device__ __forceinline__ Layout state_layout(int nx, int ny, int es) {
-  if (9ull * es * (unsigned long long)nx * (unsigned long long)ny <= 0xFFFFFFFFull)
-    return {(size_t)nx, 9u * (unsigned)nx};
-  return {plane_elems(nx, ny, es), (unsigned)nx};
+__host__ __device__ __forceinline__ Layout state_layout(int nx, int, int) { return {(size_t)nx, 9u * (unsigned)nx}; }
+
+// Byte offsets of a state from uniform bases fit the 32-bit lane offsets
+// when 9 es nx ny < 2^32 (always for the 2-byte storages; FP32 lattices up
+// to 119M nodes): kAbs.  Larger FP32 states are read per tile relative to
+// the band of rows the tile reads (kBand: tile rows whose halo stays inside
+// the lattice) or with 64-bit addresses (kWide: the tile rows that wrap),
+// in two launches, so that the wide path adds no registers to the kernel
+// that runs nearly every tile.
+enum { kAbs = 0, kBand = 1, kWide = 2 };
+__host__ __device__ __forceinline__ bool wide_state(int nx, int ny, int es) {
+  return 9ull * (unsigned long long)es * (unsigned long long)nx * (unsigned long long)ny > 0xFFFFFFFFull;
 }
+
+// Tile rows of one launch: local tile row r is row r0 + r for r < na, else
+// r1 + (r - na) (the wide launch takes the rows at both ends).
+struct TileRows {
+  int r0, na, r1;
+};
+__device__ __forceinline__ int tile_row(const TileRows& t, int r) { return r < t.na ? t.r0 + r : t.r1 + (r - t.na); }
 
 // Layout of an adjoint state buffer: eleven fields (L_0..L_8, A_x, A_y)
 // with rows interleaved like the FP32 state when every byte offset fits 32
@@ -209,6 +224,18 @@ __device__ __forceinline__ void pull_raw(const Planes<E>& P, const NodeAddr<size
   r[6] = ldb<E>(P.p[6], a.rm + a.cp);
   r[7] = ldb<E>(P.p[7], a.rp + a.cp);
   r[8] = ldb<E>(P.p[8], a.rp + a.cm);
+}
+
+// Populations arriving at node (x, y) from a row-interleaved FP32 state,
+// any node (periodic wrap), with 64-bit addresses (kWide).
+__device__ __forceinline__ void pull_rows(const char* __restrict__ base, int x, int y, int nx, int ny, float* r) {
+  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+  const int row[9] = {y, y, ym, y, yp, ym, ym, yp, yp};  // source of population i: (x, y) - e_i
+  const int col[9] = {x, xm, x, xp, x, xm, xp, xp, xm};
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+    r[i] = *reinterpret_cast<const float*>(base + 4 * (((size_t)row[i] * 9 + i) * nx + col[i]));
 }
 
 // Decode the raw values of a node into f_i (FP32).  rref is the node's
@@ -335,14 +362,28 @@ __device__ __forceinline__ bool interior_tile(int x0, int y0, int nx, int ny) {
   return x0 >= 2 && y0 >= 2 && x0 + S::TX + 2 <= nx && y0 + S::TY + 2 <= ny;
 }
 
-// Issue the loads of the tile at (x0, y0); ring loads first.  kInterior
-// (interior_tile true): every population's pull shift goes into its uniform
-// base, so the nine loads of a node share one offset register.
-template <class S, class St, bool kInterior = false>
+// Issue the loads of the tile at (x0, y0); ring loads first.  P holds the
+// population bases of lattice row yb (0, or the tile's band origin y0 - 2
+// for kBand); offsets count rows from there.  kInterior (interior_tile
+// true): every population's pull shift goes into its uniform base, so the
+// nine loads of a node share one offset register.  kWideAddr: 64-bit
+// addresses from the state's base P.p[0] (FP32, rows that wrap).
+template <class S, class St, bool kInterior = false, bool kWideAddr = false>
 __device__ __forceinline__ void issue_tile(const Planes<typename St::E>& P, const uint16_t* __restrict__ rho_ref,
-                                           int nx, int ny, int x0, int y0, TileRegs<S, St>& R) {
+                                           int nx, int ny, int x0, int y0, int yb, TileRegs<S, St>& R) {
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * S::TX + tx;
-  if constexpr (kInterior) {
+  if constexpr (kWideAddr) {
+    static_assert(sizeof(typename St::E) == 4 && !St::kRef, "64-bit addressing is for FP32 states");
+    if (tid < S::NRING) {
+      int hx, hy;
+      ring_slot<S>(tid, hx, hy);
+      pull_rows(P.p[0], wrap(x0 + hx - 1, nx), wrap(y0 + hy - 1, ny), nx, ny, R.rraw);
+    }
+    const int xw = wrap(x0 + tx, nx);
+#pragma unroll
+    for (int k = 0; k < S::NPT; ++k) pull_rows(P.p[0], xw, wrap(y0 + ty + k * S::WY, ny), nx, ny, R.raw[k]);
+    return;
+  } else if constexpr (kInterior) {
     using E = typename St::E;
     const unsigned rb = St::ES * state_layout(nx, ny, St::ES).rp;
     Planes<E> Q;  // Q_i + offset(x) = P_i + offset(x - e_i)
@@ -352,12 +393,12 @@ __device__ __forceinline__ void issue_tile(const Planes<typename St::E>& P, cons
     if (tid < S::NRING) {
       int hx, hy;
       ring_slot<S>(tid, hx, hy);
-      const unsigned off = (unsigned)(y0 + hy - 1) * rb + (unsigned)(x0 + hx - 1) * St::ES;
+      const unsigned off = (unsigned)(y0 + hy - 1 - yb) * rb + (unsigned)(x0 + hx - 1) * St::ES;
 #pragma unroll
       for (int i = 0; i < 9; ++i) R.rraw[i] = ldb<E>(Q.p[i], off);
       if constexpr (St::kRef) R.rrref = ldb<uint16_t>(rref, 2u * ((unsigned)(y0 + hy - 1) * nx + (unsigned)(x0 + hx - 1)));
     }
-    const unsigned off0 = (unsigned)(y0 + ty) * rb + (unsigned)(x0 + tx) * St::ES;
+    const unsigned off0 = (unsigned)(y0 + ty - yb) * rb + (unsigned)(x0 + tx) * St::ES;
 #pragma unroll
     for (int k = 0; k < S::NPT; ++k) {
       const unsigned off = off0 + (unsigned)(k * S::WY) * rb;
@@ -371,14 +412,14 @@ __device__ __forceinline__ void issue_tile(const Planes<typename St::E>& P, cons
     int hx, hy;
     ring_slot<S>(tid, hx, hy);
     const int gx = wrap(x0 + hx - 1, nx), gy = wrap(y0 + hy - 1, ny);
-    pull_raw<typename St::E>(P, node_addr<St::ES>(gx, gy, nx, ny, state_layout(nx, ny, St::ES).rp), R.rraw);
+    pull_raw<typename St::E>(P, node_addr<St::ES>(gx, gy, nx, ny, state_layout(nx, ny, St::ES).rp, yb), R.rraw);
     if constexpr (St::kRef) R.rrref = rho_ref[(size_t)gy * nx + gx];
   }
   const int xw = wrap(x0 + tx, nx);
 #pragma unroll
   for (int k = 0; k < S::NPT; ++k) {
     const int yw = wrap(y0 + ty + k * S::WY, ny);
-    pull_raw<typename St::E>(P, node_addr<St::ES>(xw, yw, nx, ny, state_layout(nx, ny, St::ES).rp), R.raw[k]);
+    pull_raw<typename St::E>(P, node_addr<St::ES>(xw, yw, nx, ny, state_layout(nx, ny, St::ES).rp, yb), R.raw[k]);
     if constexpr (St::kRef) R.rref[k] = rho_ref[(size_t)yw * nx + xw];
   }
 }
@@ -433,35 +474,42 @@ __device__ __forceinline__ void neighbours(const float* srho, int hx, int hy, fl
 // Step kernel: one tile per workgroup, tiles ordered across the XCDs by
 // xcd_tile so that neighbouring tiles (whose halo lines overlap) run on the
 // same XCD and share its L2.
-template <class S, class St>
+template <class S, class St, int kMode = kAbs>
 __global__ __launch_bounds__(S::NTHREADS) void step_kernel(const void* __restrict__ src, void* __restrict__ dst,
                                                            const uint16_t* __restrict__ ref_in,
                                                            uint16_t* __restrict__ ref_out, int nx, int ny, int ntx,
-                                                           int ntiles, int strip, Coef<float> c, RefPoly<float> q) {
+                                                           int ntiles, int strip, Coef<float> c, RefPoly<float> q,
+                                                           TileRows rows) {
   using E = typename St::E;
   __shared__ float srho[S::LDS];
   __shared__ float sref[St::kRef ? 3 * S::LDS : 1];
   const Layout L = state_layout(nx, ny, St::ES);
-  const size_t N = L.ps;
+  const size_t N = L.ps, rowb = (size_t)St::ES * L.rp;
   int tx, ty;
   strip_tile(xcd_tile(blockIdx.x, ntiles), ntx, ntiles / ntx, strip, tx, ty);
-  const int x0 = tx * S::TX, y0 = ty * S::TY;
+  const int x0 = tx * S::TX, y0 = tile_row(rows, ty) * S::TY;
   float f[S::NPT][9];
   float rho[S::NPT];
   {
     TileRegs<S, St> R;
-    if (interior_tile<S>(x0, y0, nx, ny))
-      issue_tile<S, St, true>(planes<E>(src, N), ref_in, nx, ny, x0, y0, R);
+    const int yb = kMode == kBand ? y0 - 2 : 0;  // loads: rows counted from yb
+    const char* sb = static_cast<const char*>(src) + (size_t)yb * rowb;
+    if constexpr (kMode == kWide)
+      issue_tile<S, St, false, true>(planes<E>(src, N), ref_in, nx, ny, x0, y0, 0, R);
+    else if (interior_tile<S>(x0, y0, nx, ny))
+      issue_tile<S, St, true>(planes<E>(sb, N), ref_in, nx, ny, x0, y0, yb, R);
     else
-      issue_tile<S, St, false>(planes<E>(src, N), ref_in, nx, ny, x0, y0, R);
+      issue_tile<S, St, false>(planes<E>(sb, N), ref_in, nx, ny, x0, y0, yb, R);
     stage_tile<S, St>(R, q, f, rho, srho, St::kRef ? sref : nullptr);
   }
   __syncthreads();
   const int x = x0 + threadIdx.x;
   if (x >= nx) return;
-  const OutPlanes<E> Q = out_planes<E>(dst, N);
-  const unsigned rb = St::ES * L.rp;  // also the row pitch of the 2-byte reference planes (rp = nx)
-  const unsigned o0 = rb * (unsigned)(y0 + threadIdx.y) + St::ES * (unsigned)x;
+  // stores: rows counted from row 0 (kAbs) or from the tile's first row
+  const int ys = kMode == kAbs ? 0 : y0;
+  const OutPlanes<E> Q = out_planes<E>(static_cast<char*>(dst) + (size_t)ys * rowb, N);
+  const unsigned rb = St::ES * L.rp;
+  const unsigned o0 = rb * (unsigned)(y0 - ys + threadIdx.y) + St::ES * (unsigned)x;
 #pragma unroll
   for (int k = 0; k < S::NPT; ++k) {
     const int ly = threadIdx.y + k * S::WY, y = y0 + ly;
@@ -491,7 +539,7 @@ __global__ __launch_bounds__(S::NTHREADS) void step_kernel(const void* __restric
 
 // Moments: rho and u of main Eq. 5 plus per-workgroup FP64 partial sums of
 // mass and lattice momentum (reduced in a fixed order).
-template <class St>
+template <class St, bool kWideAddr = false>
 __global__ __launch_bounds__(MomTile::NTHREADS) void moments_kernel(
     const void* __restrict__ src, const uint16_t* __restrict__ ref_in, float* __restrict__ rho_out,
     float* __restrict__ ux_out, float* __restrict__ uy_out, double* __restrict__ partials, int nx, int ny, int ntx,
@@ -505,7 +553,7 @@ __global__ __launch_bounds__(MomTile::NTHREADS) void moments_kernel(
   float rho[S::NPT];
   {
     TileRegs<S, St> R;
-    issue_tile<S, St>(planes<typename St::E>(src, N), ref_in, nx, ny, x0, y0, R);
+    issue_tile<S, St, false, kWideAddr>(planes<typename St::E>(src, N), ref_in, nx, ny, x0, y0, 0, R);
     stage_tile<S, St>(R, q, f, rho, srho, nullptr);
   }
   __syncthreads();
@@ -631,7 +679,15 @@ __global__ __launch_bounds__(BLK) void get_state_kernel(const void* __restrict__
   const int x = (int)(o % nx), y = (int)(o / nx);
   E raw[9];
   const Layout L = state_layout(nx, ny, St::ES);
-  pull_raw<E>(planes<E>(src, L.ps), node_addr<St::ES>(x, y, nx, ny, L.rp), raw);
+  if constexpr (!St::kRef) {
+    if (wide_state(nx, ny, St::ES)) {
+      pull_rows(static_cast<const char*>(src), x, y, nx, ny, raw);
+    } else {
+      pull_raw<E>(planes<E>(src, L.ps), node_addr<St::ES>(x, y, nx, ny, L.rp), raw);
+    }
+  } else {
+    pull_raw<E>(planes<E>(src, L.ps), node_addr<St::ES>(x, y, nx, ny, L.rp), raw);
+  }
   float f[9];
   decode<St>(raw, St::kRef ? ref_in[o] : 0, q, f);
 #pragma unroll
@@ -761,7 +817,7 @@ __device__ __forceinline__ void block_accumulate(const float* th, double* red, d
 // Every global load (the forward populations with their ring, the A halo and
 // the adjoint populations of the own nodes) is issued before the first
 // barrier.
-template <class S, bool kInterior>
+template <class S, bool kInterior, int kMode>
 __device__ __forceinline__ void adjoint_tile(const float* __restrict__ fsrc, const float* __restrict__ adj_in,
                                              float* __restrict__ adj_out, int nx, int ny, int x0, int y0,
                                              const Coef<float>& c, float* srho, float* snu, float* sa, float* th) {
@@ -777,7 +833,13 @@ __device__ __forceinline__ void adjoint_tile(const float* __restrict__ fsrc, con
   AHalo<S> h;
   {
     TileRegs<S, StoreF32> R;
-    issue_tile<S, StoreF32, kInterior>(planes<float>(fsrc, state_layout(nx, ny, 4).ps), nullptr, nx, ny, x0, y0, R);
+    const Layout Ls = state_layout(nx, ny, 4);
+    const int yb = kMode == kBand ? y0 - 2 : 0;  // forward state: rows counted from yb
+    if constexpr (kMode == kWide)
+      issue_tile<S, StoreF32, false, true>(planes<float>(fsrc, Ls.ps), nullptr, nx, ny, x0, y0, 0, R);
+    else
+      issue_tile<S, StoreF32, kInterior>(planes<float>(reinterpret_cast<const char*>(fsrc) + (size_t)yb * 4 * Ls.rp, Ls.ps),
+                                         nullptr, nx, ny, x0, y0, yb, R);
     load_a<S, kInterior>(adj_in + 9 * N, adj_in + 10 * N, nx, ny, A.rp, x0, y0, h);
     // lam-bar_i(y) = L_i(y + e_i) (+ nu(y + e_i) below)
 #pragma unroll
@@ -827,24 +889,27 @@ __device__ __forceinline__ void adjoint_tile(const float* __restrict__ fsrc, con
   }
 }
 
-template <class S>
+template <class S, int kMode = kAbs>
 __global__ __launch_bounds__(S::NTHREADS) void adjoint_step_kernel(const float* __restrict__ fsrc,
                                                                    const float* __restrict__ adj_in,
                                                                    float* __restrict__ adj_out,
                                                                    double* __restrict__ partials, int nx, int ny,
-                                                                   int ntx, int ntiles, int strip, Coef<float> c) {
+                                                                   int ntx, int ntiles, int strip, Coef<float> c,
+                                                                   TileRows rows) {
   using L = AdjLds<S>;
   __shared__ float srho[S::LDS];
   __shared__ float snu[S::LDS];
   __shared__ __align__(8) float sa[L::NSA];
   int tx, ty;
   strip_tile(xcd_tile(blockIdx.x, ntiles), ntx, ntiles / ntx, strip, tx, ty);
-  const int x0 = tx * S::TX, y0 = ty * S::TY;
+  const int x0 = tx * S::TX, y0 = tile_row(rows, ty) * S::TY;
   float th[3] = {0.0f, 0.0f, 0.0f};
-  if (interior_tile<S>(x0, y0, nx, ny))
-    adjoint_tile<S, true>(fsrc, adj_in, adj_out, nx, ny, x0, y0, c, srho, snu, sa, th);
+  if constexpr (kMode == kWide)  // the tile rows that wrap: never interior
+    adjoint_tile<S, false, kWide>(fsrc, adj_in, adj_out, nx, ny, x0, y0, c, srho, snu, sa, th);
+  else if (interior_tile<S>(x0, y0, nx, ny))
+    adjoint_tile<S, true, kMode>(fsrc, adj_in, adj_out, nx, ny, x0, y0, c, srho, snu, sa, th);
   else
-    adjoint_tile<S, false>(fsrc, adj_in, adj_out, nx, ny, x0, y0, c, srho, snu, sa, th);
+    adjoint_tile<S, false, kMode>(fsrc, adj_in, adj_out, nx, ny, x0, y0, c, srho, snu, sa, th);
   block_accumulate<S>(th, reinterpret_cast<double*>(sa), partials);
 }
 
@@ -1070,12 +1135,41 @@ int tiles_total(int nx, int ny) { return tiles_x<S>(nx) * ((ny + S::TY - 1) / S:
 
 // One step of storage St with tile shape S from the buffer src (and its
 // reference plane) to dst, on the context's stream.
+// Tile rows [lo, hi) whose reads stay inside the lattice (t TY >= 2 and
+// t TY + TY + 2 <= ny): the kBand launch of a wide state.
+template <class S>
+void band_rows(int ny, int& lo, int& hi) {
+  lo = (2 + S::TY - 1) / S::TY;
+  hi = ny >= S::TY + 2 ? (ny - S::TY - 2) / S::TY + 1 : 0;
+  if (hi < lo) hi = lo;
+}
+
+// Launch fn(mode, rows, nrows) over every tile row of a lattice: one kAbs
+// launch, or for a wide FP32 state a kBand launch over the band rows and a
+// kWide launch over the rows at both ends.
+template <class S, bool kFP32, class Fn>
+void for_tile_rows(int nx, int ny, Fn&& fn) {
+  const int nty = (ny + S::TY - 1) / S::TY;
+  if constexpr (kFP32) {
+    if (wide_state(nx, ny, 4)) {
+      int lo, hi;
+      band_rows<S>(ny, lo, hi);
+      if (hi > lo) fn(std::integral_constant<int, kBand>{}, TileRows{lo, hi - lo, 0}, hi - lo);
+      fn(std::integral_constant<int, kWide>{}, TileRows{0, lo, hi}, lo + nty - hi);
+      return;
+    }
+  }
+  fn(std::integral_constant<int, kAbs>{}, TileRows{0, nty, 0}, nty);
+}
+
 template <class St, class S>
 void launch_step_tiles(const lbm_ctx* ctx, const void* src, void* dst, const uint16_t* ref_in, uint16_t* ref_out) {
-  const int nx = ctx->p.nx, ny = ctx->p.ny;
-  step_kernel<S, St><<<tiles_total<S>(nx, ny), dim3(S::TX, S::WY), 0, ctx->stream>>>(
-      src, dst, ref_in, ref_out, nx, ny, tiles_x<S>(nx), tiles_total<S>(nx, ny),
-      strip_width(nx, S::TX, St::kRef), ctx->c, ctx->q);
+  const int nx = ctx->p.nx, ny = ctx->p.ny, ntx = tiles_x<S>(nx);
+  for_tile_rows<S, !St::kRef>(nx, ny, [&](auto mode, TileRows rows, int nrows) {
+    step_kernel<S, St, decltype(mode)::value><<<ntx * nrows, dim3(S::TX, S::WY), 0, ctx->stream>>>(
+        src, dst, ref_in, ref_out, nx, ny, ntx, ntx * nrows, strip_width(nx, S::TX, St::kRef), ctx->c, ctx->q,
+        rows);
+  });
 }
 
 // Smaller tiles for small lattices: the storage's own tile while it gives at
@@ -1288,9 +1382,20 @@ int lbm_moments(lbm_ctx* ctx, float* rho, float* ux, float* uy, double totals[3]
   using S = MomTile;
   int st = with_storage(ctx, [&](auto store) -> int {
     using St = decltype(store);
-    moments_kernel<St><<<tiles_total<S>(ctx->p.nx, ctx->p.ny), dim3(S::TX, S::WY), 0, ctx->stream>>>(
-        ctx->buf[ctx->cur], ctx->ref[ctx->cur], rho, ux, uy, ctx->scratch, ctx->p.nx, ctx->p.ny,
-        tiles_x<S>(ctx->p.nx), ctx->c, ctx->q);
+    auto go = [&](auto wide) {
+      moments_kernel<St, decltype(wide)::value><<<tiles_total<S>(ctx->p.nx, ctx->p.ny), dim3(S::TX, S::WY), 0,
+                                                  ctx->stream>>>(ctx->buf[ctx->cur], ctx->ref[ctx->cur], rho, ux, uy,
+                                                                 ctx->scratch, ctx->p.nx, ctx->p.ny,
+                                                                 tiles_x<S>(ctx->p.nx), ctx->c, ctx->q);
+    };
+    if constexpr (!St::kRef) {
+      if (wide_state(ctx->p.nx, ctx->p.ny, 4))
+        go(std::true_type{});
+      else
+        go(std::false_type{});
+    } else {
+      go(std::false_type{});
+    }
     HIP_OK(hipGetLastError());
     return LBM_OK;
   });
@@ -1388,17 +1493,26 @@ int lbm_adjoint_seed(lbm_ctx* ctx, const float* lam, void* adj) {
   return LBM_OK;
 }
 
+// One adjoint step on the context's stream (split like the forward step for
+// wide FP32 states).  Blocks of both launches add into the partial-sum
+// slots 0 .. grid-1 in launch order, so the sums stay reproducible.
+static void launch_adjoint(const lbm_ctx* ctx, const void* f_t, const void* adj_next, void* adj_out) {
+  using S = AdjTile;
+  const int nx = ctx->p.nx, ny = ctx->p.ny, ntx = tiles_x<S>(nx);
+  for_tile_rows<S, true>(nx, ny, [&](auto mode, TileRows rows, int nrows) {
+    adjoint_step_kernel<S, decltype(mode)::value><<<ntx * nrows, dim3(S::TX, S::WY), 0, ctx->stream>>>(
+        static_cast<const float*>(f_t), static_cast<const float*>(adj_next), static_cast<float*>(adj_out),
+        ctx->theta, nx, ny, ntx, ntx * nrows, strip_width(nx, S::TX, false), ctx->c, rows);
+  });
+}
+
 int lbm_adjoint_step(lbm_ctx* ctx, const void* f_t, const void* adj_next, void* adj_out) {
   if (int st = check_ctx(ctx, false)) return st;
   if (int st = need_fp32(ctx, "the adjoint")) return st;
   if (!f_t || !adj_next || !adj_out || adj_next == adj_out)
     return fail(LBM_EINVAL, "f_t, adj_next and adj_out must be device buffers, adj_next != adj_out");
   if (int st = set_device(ctx)) return st;
-  using S = AdjTile;
-  const int ntx = tiles_x<S>(ctx->p.nx), ntiles = ctx->adj_blocks;
-  adjoint_step_kernel<S><<<ntiles, dim3(S::TX, S::WY), 0, ctx->stream>>>(
-      static_cast<const float*>(f_t), static_cast<const float*>(adj_next), static_cast<float*>(adj_out),
-      ctx->theta, ctx->p.nx, ctx->p.ny, ntx, ntiles, strip_width(ctx->p.nx, S::TX, false), ctx->c);
+  launch_adjoint(ctx, f_t, adj_next, adj_out);
   HIP_OK(hipGetLastError());
   return LBM_OK;
 }
@@ -1414,15 +1528,10 @@ int lbm_adjoint_run(lbm_ctx* ctx, const void* const* f_states, int32_t n, void* 
   for (int32_t j = 0; j < n; ++j)
     if (!f_states[j]) return fail(LBM_EINVAL, "f_states[%d] is NULL", j);
   if (int st = set_device(ctx)) return st;
-  using S = AdjTile;
-  const int ntx = tiles_x<S>(ctx->p.nx), ntiles = ctx->adj_blocks;
   void* buf[2] = {adj_a, adj_b};
   int cur = 0;
   for (int32_t j = n - 1; j >= 0; --j) {
-    adjoint_step_kernel<S><<<ntiles, dim3(S::TX, S::WY), 0, ctx->stream>>>(
-        static_cast<const float*>(f_states[j]), static_cast<const float*>(buf[cur]),
-        static_cast<float*>(buf[cur ^ 1]), ctx->theta, ctx->p.nx, ctx->p.ny, ntx, ntiles,
-        strip_width(ctx->p.nx, S::TX, false), ctx->c);
+    launch_adjoint(ctx, f_states[j], buf[cur], buf[cur ^ 1]);
     cur ^= 1;
   }
   HIP_OK(hipGetLastError());

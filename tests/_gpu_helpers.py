@@ -66,14 +66,11 @@ def device_samples(f_dev, points):
 
 def fp32_state_of(buf, nx, ny):
     """The nine populations (9, ny*nx) held by an FP32 state or checkpoint
-    buffer.  Its internal layout interleaves rows (population i of node
-    (x, y) at element (9 y + i) nx + x) when 36 nx ny < 2^32, and holds nine
-    padded planes otherwise (planes_of); the rest of the buffer holds no
+    buffer.  Its internal layout interleaves rows: population i of node
+    (x, y) at element (9 y + i) nx + x; the rest of the buffer holds no
     data."""
     n = nx * ny
-    if 36 * n <= 0xFFFFFFFF:
-        return buf[: 9 * n * 4].view(torch.float32).view(ny, 9, nx).permute(1, 0, 2).reshape(9, n)
-    return planes_of(buf, nx, ny, 9)
+    return buf[: 9 * n * 4].view(torch.float32).view(ny, 9, nx).permute(1, 0, 2).reshape(9, n)
 
 
 def adj_state_of(buf, nx, ny):
@@ -88,8 +85,8 @@ def adj_state_of(buf, nx, ny):
 
 def planes_of(buf, nx, ny, nplanes, es=4):
     """The nplanes data regions (nplanes, ny*nx) of an internal byte buffer
-    in plane layout (states and adjoint states of lattices too large for
-    interleaved rows): planes P elements apart,
+    in plane layout (adjoint states of lattices too large for interleaved
+    rows): planes P elements apart,
     with P = nx*ny rounded up to 64 plus 16640 bytes' worth of elements
     (include/lbm.h); the padding between planes holds no data."""
     p = -(-nx * ny // 64) * 64 + 16640 // es

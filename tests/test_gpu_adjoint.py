@@ -91,26 +91,33 @@ def test_adjoint_step_matches_oracle(case):
     assert np.all(np.abs(dth - ref_th) <= 1e-5 * scale), (dth, ref_th, scale)
 
 
-def test_adjoint_step_sampled_spinodal_4096():
-    """One adjoint step on the 4096^2 spinodal workload (T_r = 0.7, W = 10,
-    after 50 forward steps), whose state and adjoint state interleave rows
-    and whose tiles run in strip order: Lambda(t) at sampled nodes, interior
-    and on the periodic edges, against the oracle's exact VJP on a 15 x 15
-    periodic crop of f(t) and Lambda(t+1) around each.  Lambda(t) at a node
-    reads f(t) and Lambda(t+1) within two nodes (streaming and the force
-    stencil), so the crop's seam, seven nodes out, is beyond its reach."""
-    n, half = 4096, 7
-    _, co = params_pair(n, n, tr=0.7, width=10.0)
-    lat = lattice(n, n, wl.spinodal(co, n=n), tr=0.7, width=10.0)
+@pytest.mark.parametrize("nx,ny", [(4096, 4096), (16384, 8192)])
+def test_adjoint_step_sampled(nx, ny):
+    """One adjoint step on a spinodal field (mean of the coexistence
+    densities +- 0.01, T_r = 0.7, W = 10, after 50 forward steps): 4096^2,
+    whose state and adjoint state interleave rows read through 32-bit
+    offsets, and 16384 x 8192, whose state is read relative to each tile's
+    row band and with 64-bit addresses in the tile rows that wrap.  Lambda(t)
+    at sampled nodes, interior and on the periodic edges, against the
+    oracle's exact VJP on a 15 x 15 periodic crop of f(t) and Lambda(t+1)
+    around each.  Lambda(t) at a node reads f(t) and Lambda(t+1) within two
+    nodes (streaming and the force stencil), so the crop's seam, seven
+    nodes out, is beyond its reach."""
+    half = 7
+    _, co = params_pair(nx, ny, tr=0.7, width=10.0)
+    rho = wl.uniform_noise(nx, ny, 0.5 * (co.rho_g + co.rho_l), 0.01, seed=3)
+    lat = lattice(nx, ny, rho, tr=0.7, width=10.0)
     lat.step(50)
     ck = lat.save_state()
     f = lat.state()
     gen = torch.Generator(device=DEV).manual_seed(11)
-    lam = torch.randn((9, n, n), generator=gen, device=DEV)
+    lam = torch.randn((9, ny, nx), generator=gen, device=DEV)
     a, b = lat.adjoint_seed(lam), lat.adjoint_buffer()
     lat.adjoint_step(ck, a, b)
     got_all = lat.adjoint_get(b)
-    for x, y in [(2047, 2048), (0, 0), (n - 1, n - 1), (0, n - 1), (1234, 7), (n - 2, 3000)]:
+    pts = [(nx // 2 - 1, ny // 2), (0, 0), (nx - 1, ny - 1), (0, ny - 1), (1234, 7), (nx - 2, 3000), (77, 1),
+           (nx - 1, ny - 9)]
+    for x, y in pts:
         fc = crop_periodic(f, x, y, half).double().cpu().numpy()
         lc = crop_periodic(lam, x, y, half).double().cpu().numpy()
         ref = adj.step_vjp(fc, lc, co)[:, half, half]

@@ -256,8 +256,8 @@ def test_sampled_parity_coalescence_16384x8192():
 
 def test_sampled_parity_largest_lattice():
     """The largest lattice the library accepts, 16384 x 14563 (9 nx ny just
-    below 2^31; its FP32 state too large for interleaved rows, so nine
-    planes with byte offsets inside a plane up to 0.95 GB): the spinodal
+    below 2^31; its FP32 state, 8.6 GB, is read relative to each tile's row
+    band and, in the tile rows that wrap, with 64-bit addresses): the spinodal
     field (T_r = 0.7, mean of the coexistence densities +- 0.01, seed 3),
     5 steps, sampled nodes against oracle light-cone crops, including the
     last row and column."""
@@ -277,12 +277,13 @@ def test_sampled_parity_largest_lattice():
 
 @pytest.mark.parametrize("ny", [7281, 7282])
 def test_sampled_parity_at_the_row_layout_limit(ny):
-    """FP32 states interleave rows while every byte offset fits 32 bits
-    (36 nx ny < 2^32): 16384 x 7281 is the tallest such lattice of that
-    width (largest offset 4 294 508 540 bytes), 16384 x 7282 the first that
-    falls back to nine planes.  Spinodal field (T_r = 0.7), 5 steps,
-    sampled nodes against oracle crops, including the last row, whose
-    offsets are the largest."""
+    """FP32 states are read through 32-bit offsets from uniform bases while
+    36 nx ny < 2^32: 16384 x 7281 is the tallest such lattice of that width
+    (largest offset 4 294 508 540 bytes); 16384 x 7282 is the first read
+    relative to each tile's row band, with 64-bit addresses for the tile
+    rows that wrap.  Spinodal field (T_r = 0.7), 5 steps, sampled nodes
+    against oracle crops, including the last row, whose offsets are the
+    largest."""
     nx, steps = 16384, 5
     assert (36 * nx * ny < 2 ** 32) == (ny == 7281)
     _, co = params_pair(nx, ny, tr=0.7, width=10.0)
