@@ -121,12 +121,9 @@ int lbm_sigma_paper(double width, double tr, double a, double b, double r_gas,
 /* Bytes of ONE distribution buffer (the caller provides two, A and B):
  * 9*P*4 for LBM_FP32 and 9*P*2 for the 2-byte storages, with P = nx*ny
  * rounded up to a multiple of 64 plus 16640 bytes' worth of elements
- * (16640/4 or 16640/2).  The layout inside is internal: buffers with
- * 9*es*nx*ny < 2^32 (es = 4 or 2 bytes per population) interleave rows
- * (the nine populations of a lattice row are nine consecutive rows of the
- * buffer); larger ones hold nine planes P elements apart, so that the
- * planes do not start at one offset modulo a large power of two.  0 on
- * error. */
+ * (16640/4 or 16640/2).  The layout inside is internal: the rows are
+ * interleaved (the nine populations of a lattice row are nine consecutive
+ * rows of the buffer, 9*nx*ny*es bytes in all).  0 on error. */
 size_t lbm_state_bytes(const lbm_params* p);
 
 /* Bytes of the reference-density buffer the 2-byte storages need (two

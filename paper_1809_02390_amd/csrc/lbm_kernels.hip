@@ -2,11 +2,12 @@
 // (gfx950).  See include/lbm.h for the contract of every entry point.
 //
 // Data layout, x fastest.  State buffers (state_layout) interleave rows,
-// population i of node (x, y) at element (9 y + i) nx + x, when every byte
-// offset fits 32 bits; otherwise they hold nine planes, population i at
-// i*P with P = plane_elems (nx*ny rounded up to 64 plus a pad, so that the
-// planes do not start at one offset modulo a large power of two).  The
-// adjoint state does the same with eleven fields (adj_layout); the 2-byte
+// population i of node (x, y) at element (9 y + i) nx + x (FP32 states
+// larger than 4 GiB are read with band-relative or 64-bit offsets,
+// wide_state).  The adjoint state interleaves its eleven fields the same
+// way when its offsets fit 32 bits, else it holds eleven planes P =
+// plane_elems apart (nx*ny rounded up to 64 plus a pad, so that the planes
+// do not start at one offset modulo a large power of two); the 2-byte
 // reference densities and the caller's plain arrays hold planes of nx*ny.  Two caller-owned
 // buffers A and B alternate; the buffer that is
 // read by the next step holds the post-collision populations of the previous
