@@ -57,6 +57,20 @@ def sampled_oracle(co, rho0, points, nsteps):
     return np.array(out)
 
 
+def sampled_oracle_moments(co, rho0, points, nsteps):
+    """Oracle rho, u_x, u_y (main Eq. 5) at each sample point after nsteps,
+    from the same light-cone crops as sampled_oracle (the force stencil
+    reads one node beyond the point, inside the crop's valid region)."""
+    half = 2 * nsteps + 3
+    out = []
+    for (x, y) in points:
+        crop = crop_periodic(np.asarray(rho0, np.float64), x, y, half)
+        f = lbm.run(lbm.equilibrium(crop, co), co, nsteps, lbm.collide_sequence)
+        r, u, v = lbm.macroscopic(f, co)
+        out.append((r[half, half], u[half, half], v[half, half]))
+    return np.array(out)
+
+
 def device_samples(f_dev, points):
     """f at the sample points from a device state tensor (9, ny, nx)."""
     xs = torch.tensor([p[0] for p in points], device=f_dev.device)

@@ -10,7 +10,7 @@ import paper_1809_02390_amd as pkg
 import workloads as wl
 from oracle import lbm, measure
 from tests._gpu_helpers import (crop_periodic, device_samples, lattice, oracle_init, params_pair,
-                                sampled_oracle)
+                                sampled_oracle, sampled_oracle_moments)
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -260,7 +260,8 @@ def test_sampled_parity_largest_lattice():
     band and, in the tile rows that wrap, with 64-bit addresses): the spinodal
     field (T_r = 0.7, mean of the coexistence densities +- 0.01, seed 3),
     5 steps, sampled nodes against oracle light-cone crops, including the
-    last row and column."""
+    last row and column; rho and u from lbm_moments at the same nodes and
+    the FP64 total mass."""
     nx, ny, steps = 16384, 14563, 5
     _, co = params_pair(nx, ny, tr=0.7, width=10.0)
     rho = wl.uniform_noise(nx, ny, 0.5 * (co.rho_g + co.rho_l), 0.01, seed=3)
@@ -271,8 +272,16 @@ def test_sampled_parity_largest_lattice():
     st = lat.state()
     got = device_samples(st, pts)
     del st
-    lat.close()
     assert np.abs(got - ref).max() / co.rho_l <= TOL
+    # moments of the same state (64-bit addresses for this size)
+    ref_m = sampled_oracle_moments(co, rho, pts, steps)
+    r, u, v, tot = lat.moments()
+    got_m = np.array([[float(a[y, x]) for a in (r, u, v)] for (x, y) in pts])
+    del r, u, v
+    lat.close()
+    assert np.abs(got_m[:, 0] - ref_m[:, 0]).max() / co.rho_l <= TOL
+    assert np.abs(got_m[:, 1:] - ref_m[:, 1:]).max() < 1e-5
+    assert tot[0] == pytest.approx(float(np.asarray(rho, np.float32).astype(np.float64).sum()), rel=1e-6)
 
 
 @pytest.mark.parametrize("ny", [7281, 7282])
