@@ -284,22 +284,24 @@ def test_sampled_parity_largest_lattice():
     assert tot[0] == pytest.approx(float(np.asarray(rho, np.float32).astype(np.float64).sum()), rel=1e-6)
 
 
-@pytest.mark.parametrize("ny", [7281, 7282])
-def test_sampled_parity_at_the_row_layout_limit(ny):
+@pytest.mark.parametrize("nx,ny", [(16384, 7281), (16384, 7282), (16400, 8003)])
+def test_sampled_parity_at_the_row_layout_limit(nx, ny):
     """FP32 states are read through 32-bit offsets from uniform bases while
     36 nx ny < 2^32: 16384 x 7281 is the tallest such lattice of that width
     (largest offset 4 294 508 540 bytes); 16384 x 7282 is the first read
     relative to each tile's row band, with 64-bit addresses for the tile
-    rows that wrap.  Spinodal field (T_r = 0.7), 5 steps, sampled nodes
-    against oracle crops, including the last row, whose offsets are the
-    largest."""
-    nx, steps = 16384, 5
+    rows that wrap; 16400 x 8003 does the same with a partial last tile
+    column and a partial last tile row.  Spinodal field (T_r = 0.7), 5
+    steps, sampled nodes against oracle crops, including the last row and
+    column and nodes next to tile edges."""
+    steps = 5
     assert (36 * nx * ny < 2 ** 32) == (ny == 7281)
     _, co = params_pair(nx, ny, tr=0.7, width=10.0)
     rho = wl.uniform_noise(nx, ny, 0.5 * (co.rho_g + co.rho_l), 0.01, seed=ny)
     lat = lattice(nx, ny, rho, tr=0.7, width=10.0)
     lat.step(steps)
-    pts = [(nx - 1, ny - 1), (0, ny - 1), (nx // 2, ny - 2), (0, 0), (nx - 1, 0), (777, ny // 2)]
+    pts = [(nx - 1, ny - 1), (0, ny - 1), (nx // 2, ny - 2), (0, 0), (nx - 1, 0), (777, ny // 2),
+           (nx - 17, ny - 3), (16383 % nx, 8), (255, 7), (256, ny - 9)]
     ref = sampled_oracle(co, rho, pts, steps)
     st = lat.state()
     got = device_samples(st, pts)
