@@ -71,15 +71,20 @@ MUTS = [
 
 
 def run(j, base):
-    path, old, new, name = MUTS[j]
-    d = os.path.join(base, f"m{j:02d}")
-    shutil.copytree(ROOT, d, ignore=shutil.ignore_patterns(".git", "_work", "gpurun_out", "__pycache__",
-                                                           ".pytest_cache", "*.so", "profiles"))
-    src = open(os.path.join(d, path)).read()
-    if src.count(old) != 1:
-        return j, name, "NO-MATCH", ""
-    with open(os.path.join(d, path), "w") as fh:
-        fh.write(src.replace(old, new))
+    """Mutant j (j < 0: the unmutated control, which must pass)."""
+    path, old, new, name = MUTS[j] if j >= 0 else (MUTS[0][0], "", "", "control (no mutation)")
+    d = os.path.join(base, f"m{j:02d}" if j >= 0 else "control")
+    # the oracle's pins need only the oracle, the input generators and the tests
+    for sub in ("oracle", "workloads", "tests"):
+        shutil.copytree(os.path.join(ROOT, sub), os.path.join(d, sub),
+                        ignore=shutil.ignore_patterns("__pycache__", ".pytest_cache"))
+    shutil.copy(os.path.join(ROOT, "pytest.ini"), d)
+    if j >= 0:
+        src = open(os.path.join(d, path)).read()
+        if src.count(old) != 1:
+            return j, name, "NO-MATCH", ""
+        with open(os.path.join(d, path), "w") as fh:
+            fh.write(src.replace(old, new))
     pins = sorted(glob.glob(os.path.join(d, "tests", "test_oracle_*.py")))
     r = subprocess.run([sys.executable, "-m", "pytest", *pins, "-x", "-q", "-p", "no:cacheprovider"],
                        cwd=d, capture_output=True, text=True)
@@ -92,6 +97,11 @@ def run(j, base):
 def main(argv):
     sel = [int(a) for a in argv] or list(range(len(MUTS)))
     with tempfile.TemporaryDirectory() as base, ThreadPoolExecutor(4) as ex:
+        control = run(-1, base)
+        if control[2] != "SURVIVED":  # the unmutated copy must pass its pins
+            print("control run failed:", control[3])
+            return 1
+        print("control (no mutation): pins pass")
         res = list(ex.map(lambda j: run(j, base), sel))
     for j, name, status, first in res:
         print(f"{j:2d} {status:9s} {name:28s} {first[:110]}")
