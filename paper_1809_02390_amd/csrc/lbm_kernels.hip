@@ -538,6 +538,35 @@ __global__ __launch_bounds__(S::NTHREADS) void step_kernel(const void* __restric
   }
 }
 
+// Deterministic FP64 sum of three per-thread values over a block, into this
+// block's slot partials[3 b .. 3 b + 2] (added to it if kAdd, else stored):
+// a fixed shuffle tree inside each wave, then the waves' sums in wave order.
+// red holds 3 doubles per wave of LDS; it may alias LDS the block read
+// before the call.
+template <class S, bool kAdd>
+__device__ __forceinline__ void block_sum3(const double* in, double* red, double* __restrict__ partials) {
+  constexpr int NW = S::NTHREADS / 64;
+  const int tid = threadIdx.y * S::TX + threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double v[3] = {in[0], in[1], in[2]};
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] += __shfl_down(v[k], off, 64);
+  __syncthreads();  // red may alias LDS read above
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) red[k * NW + wave] = v[k];
+  __syncthreads();
+  if (tid < 3) {
+    double s = red[tid * NW];
+    for (int w = 1; w < NW; ++w) s += red[tid * NW + w];
+    if constexpr (kAdd)
+      partials[(size_t)blockIdx.x * 3 + tid] += s;
+    else
+      partials[(size_t)blockIdx.x * 3 + tid] = s;
+  }
+}
+
 // Moments: rho and u of main Eq. 5 plus per-workgroup FP64 partial sums of
 // mass and lattice momentum (reduced in a fixed order).
 template <class St, bool kWideAddr = false>
@@ -547,7 +576,7 @@ __global__ __launch_bounds__(MomTile::NTHREADS) void moments_kernel(
     Coef<float> c, RefPoly<float> q) {
   using S = MomTile;
   __shared__ float srho[S::LDS];
-  __shared__ double sred[3][S::NTHREADS];
+  __shared__ double sred[3 * (S::NTHREADS / 64)];
   const size_t N = state_layout(nx, ny, St::ES).ps;
   const int x0 = (blockIdx.x % ntx) * S::TX, y0 = (blockIdx.x / ntx) * S::TY;
   float f[S::NPT][9];
@@ -578,37 +607,23 @@ __global__ __launch_bounds__(MomTile::NTHREADS) void moments_kernel(
     sx += (double)m[3];
     sy += (double)m[5];
   }
-  const int tid = threadIdx.y * S::TX + threadIdx.x;
-  sred[0][tid] = sm;
-  sred[1][tid] = sx;
-  sred[2][tid] = sy;
-  __syncthreads();
-  for (int w = S::NTHREADS / 2; w > 0; w >>= 1) {
-    if (tid < w) {
-      sred[0][tid] += sred[0][tid + w];
-      sred[1][tid] += sred[1][tid + w];
-      sred[2][tid] += sred[2][tid + w];
-    }
-    __syncthreads();
-  }
-  if (tid < 3) partials[(size_t)blockIdx.x * 3 + tid] = sred[tid][0];
+  const double v[3] = {sm, sx, sy};
+  block_sum3<S, false>(v, sred, partials);
 }
 
+// Sum of the per-workgroup partials in a fixed order: each thread adds a
+// strided subset in order, then block_sum3 over the 256 threads.
 constexpr int RED = 256;
+struct FlatBlock {
+  static constexpr int TX = RED, NTHREADS = RED;
+};
 __global__ __launch_bounds__(RED) void finish_sums(const double* __restrict__ partials, int nblocks,
                                                    double* __restrict__ out) {
-  __shared__ double s[3][RED];
+  __shared__ double red[3 * (RED / 64)];
   double a[3] = {0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nblocks; b += RED)
     for (int k = 0; k < 3; ++k) a[k] += partials[(size_t)b * 3 + k];
-  for (int k = 0; k < 3; ++k) s[k][threadIdx.x] = a[k];
-  __syncthreads();
-  for (int w = RED / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
-      for (int k = 0; k < 3; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x < 3) out[threadIdx.x] = s[threadIdx.x][0];
+  block_sum3<FlatBlock, false>(a, red, out);  // one block: its slot is out[0..2]
 }
 
 // Store the post-streaming populations f of node (x, y) into the pull
@@ -789,29 +804,13 @@ __device__ __forceinline__ void stage_nu(const float* __restrict__ ax, const flo
   put_nu<S>(h, sa, snu);
 }
 
-// Deterministic FP64 block sum of three per-thread values, added to this
+// Deterministic FP64 block sum of three per-thread FP32 values, added to this
 // block's slot of partials (a block always owns the same slot, so sums over
-// many launches are reproducible bit for bit): a fixed shuffle tree inside
-// each wave, then the waves' sums in wave order.
+// many launches are reproducible bit for bit).
 template <class S>
 __device__ __forceinline__ void block_accumulate(const float* th, double* red, double* __restrict__ partials) {
-  constexpr int NW = S::NTHREADS / 64;
-  const int tid = threadIdx.y * S::TX + threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double v[3] = {(double)th[0], (double)th[1], (double)th[2]};
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) v[k] += __shfl_down(v[k], off, 64);
-  __syncthreads();  // red aliases LDS read above
-  if (lane == 0)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) red[k * NW + wave] = v[k];
-  __syncthreads();
-  if (tid < 3) {
-    double s = red[tid * NW];
-    for (int w = 1; w < NW; ++w) s += red[tid * NW + w];
-    partials[(size_t)blockIdx.x * 3 + tid] += s;
-  }
+  const double v[3] = {(double)th[0], (double)th[1], (double)th[2]};
+  block_sum3<S, true>(v, red, partials);
 }
 
 // One tile of the adjoint step (kInterior: interior_tile holds, no wrap).
@@ -1377,16 +1376,17 @@ int lbm_step(lbm_ctx* ctx, int32_t n) {
   return LBM_OK;
 }
 
-int lbm_moments(lbm_ctx* ctx, float* rho, float* ux, float* uy, double totals[3]) {
-  if (int st = check_ctx(ctx, true)) return st;
-  if (int st = set_device(ctx)) return st;
+namespace {
+// The moments kernel over the current state, its per-workgroup partials
+// into `partials` (3 per workgroup of tiles_total<MomTile>).
+int launch_moments(const lbm_ctx* ctx, float* rho, float* ux, float* uy, double* partials) {
   using S = MomTile;
-  int st = with_storage(ctx, [&](auto store) -> int {
+  return with_storage(ctx, [&](auto store) -> int {
     using St = decltype(store);
     auto go = [&](auto wide) {
       moments_kernel<St, decltype(wide)::value><<<tiles_total<S>(ctx->p.nx, ctx->p.ny), dim3(S::TX, S::WY), 0,
                                                   ctx->stream>>>(ctx->buf[ctx->cur], ctx->ref[ctx->cur], rho, ux, uy,
-                                                                 ctx->scratch, ctx->p.nx, ctx->p.ny,
+                                                                 partials, ctx->p.nx, ctx->p.ny,
                                                                  tiles_x<S>(ctx->p.nx), ctx->c, ctx->q);
     };
     if constexpr (!St::kRef) {
@@ -1400,7 +1400,13 @@ int lbm_moments(lbm_ctx* ctx, float* rho, float* ux, float* uy, double totals[3]
     HIP_OK(hipGetLastError());
     return LBM_OK;
   });
-  if (st) return st;
+}
+}  // namespace
+
+int lbm_moments(lbm_ctx* ctx, float* rho, float* ux, float* uy, double totals[3]) {
+  if (int st = check_ctx(ctx, true)) return st;
+  if (int st = set_device(ctx)) return st;
+  if (int st = launch_moments(ctx, rho, ux, uy, ctx->scratch)) return st;
   if (!totals) return LBM_OK;
   double* tot = ctx->scratch + 3 * (size_t)ctx->nblocks;
   finish_sums<<<1, RED, 0, ctx->stream>>>(ctx->scratch, ctx->nblocks, tot);
