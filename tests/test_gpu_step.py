@@ -67,6 +67,24 @@ def test_step_parity_ragged(nx, ny, steps):
     assert lat.time == steps
 
 
+def test_step_parity_sheared_droplet():
+    """Moving interface with |u| up to 0.1: a 60 x 50 droplet at T_r = 0.6,
+    W = 6 in a periodic velocity field.  A sign error in any single R, T or
+    X entry (supplement Eqs. 34, 37, 40) moves the oracle's state after 10
+    steps by >= 5e-5 rho_l (tests/test_oracle_step.py::
+    test_sheared_droplet_sees_every_correction_entry), so this gate sees
+    every entry of the cubic-velocity corrections of the kernel."""
+    _, co = params_pair(60, 50, tr=0.6, width=6.0)
+    rho, ux, uy = wl.sheared_droplet(co)
+    lat = lattice(60, 50, rho, ux, uy, tr=0.6, width=6.0)
+    f = oracle_init(co, rho, ux, uy)
+    for chunk in (1, 4, 5):
+        lat.step(chunk)
+        f = lbm.run(f, co, chunk)
+        compare(lat, f, co)
+    assert lat.time == 10
+
+
 @pytest.mark.parametrize("nx,ny", [(1, 1), (1, 64), (3, 2), (2, 5), (64, 1)])
 def test_step_parity_degenerate(nx, ny):
     """Lattices narrower than the stencil: periodic images of a node are its

@@ -354,3 +354,55 @@ def test_galilean_shear_wave_diagonal(liquid, monkeypatch):
     orig = lbm.correction_matrices
     monkeypatch.setattr(lbm, "correction_matrices", lambda ux, uy, c: tuple(0 * a for a in orig(ux, uy, c)))
     assert abs(shear_decay_ratio(liquid, 0.15, rotated=True) - 1.0) > 0.05
+
+
+# ---------------------------------------------------------------------------
+# Power of a moving-interface parity case over R, T, X (supplement Eqs. 34,
+# 37, 40): a wrong sign in any one entry must move the state well beyond
+# the FP32 parity gate, or a kernel carrying that mistake would pass parity
+# ---------------------------------------------------------------------------
+NONZERO_CORRECTIONS = [("R", 1, 1), ("R", 1, 7), ("R", 1, 8), ("T", 1, 0), ("T", 1, 1), ("X", 1, 0), ("X", 1, 1),
+                       ("R", 7, 1), ("R", 7, 7), ("T", 7, 0), ("T", 7, 1), ("X", 7, 0), ("X", 7, 1),
+                       ("R", 8, 1), ("R", 8, 8), ("T", 8, 0), ("T", 8, 1), ("X", 8, 0), ("X", 8, 1)]
+SHEAR_STEPS = 10  # the GPU parity case of tests/test_gpu_step.py runs the same state this long
+
+
+@pytest.fixture(scope="module")
+def sheared():
+    import workloads as wl
+    c = hm.derive(hm.Params(nx=60, ny=50, tr=0.6, width=6.0))
+    rho, ux, uy = wl.sheared_droplet(c)
+    return c, lbm.equilibrium(rho, c, ux, uy)
+
+
+@pytest.mark.parametrize("entry", NONZERO_CORRECTIONS, ids=lambda e: f"{e[0]}{e[1]}{e[2]}")
+def test_sheared_droplet_sees_every_correction_entry(sheared, entry, monkeypatch):
+    """60 x 50 droplet at T_r = 0.6, W = 6 in a |u| <= 0.1 periodic velocity
+    field: flipping the sign of any one of the 19 nonzero R, T, X entries
+    moves the populations after 10 steps by at least 5x the FP32 gate
+    (1e-5 rho_l), in both collision forms."""
+    c, f0 = sheared
+    ref = lbm.run(f0, c, SHEAR_STEPS)
+    orig = lbm.correction_matrices
+
+    def flipped(ux, uy, co):
+        R, T, X = orig(ux, uy, co)
+        {"R": R, "T": T, "X": X}[entry[0]][entry[1], entry[2]] *= -1.0
+        return R, T, X
+
+    monkeypatch.setattr(lbm, "correction_matrices", flipped)
+    for form in (None, lbm.collide_sequence):
+        moved = np.abs(lbm.run(f0, c, SHEAR_STEPS, form) - ref).max() / c.rho_l
+        assert moved >= 5e-5, (entry, form, moved)
+
+
+def test_sheared_droplet_corrections_are_not_negligible(sheared, monkeypatch):
+    """Removing R, T and X altogether moves the same state by far more than
+    the gate: the case sees the velocity-dependent collision as a whole."""
+    c, f0 = sheared
+    ref = lbm.run(f0, c, SHEAR_STEPS)
+    orig = lbm.correction_matrices
+    monkeypatch.setattr(lbm, "correction_matrices",
+                        lambda ux, uy, co: tuple(np.zeros_like(a) for a in orig(ux, uy, co)))
+    moved = np.abs(lbm.run(f0, c, SHEAR_STEPS) - ref).max() / c.rho_l
+    assert moved >= 1e-3, moved

@@ -128,3 +128,15 @@ def head_on(derived, speed, n=1024, diameter=128.0, gap=60.0):
     left, right = (droplets(n, n, 0.0, 1.0, w, [c], [diameter / 2]) for c in centres)
     ux = _f32(0.5 * speed * (left - right))
     return rho, ux, np.zeros_like(ux)
+
+
+def sheared_droplet(derived, nx=60, ny=50, radius=14.0, amplitude=0.1):
+    """Centred droplet in a smooth periodic velocity field
+    u = amplitude * (sin(2 pi y / ny), sin(2 pi x / nx)): the interface moves
+    at |u| up to ``amplitude`` in both directions, where the velocity-
+    dependent parts of the collision are large.  Returns (rho, ux, uy)."""
+    rho = droplets(nx, ny, _get(derived, "rho_g"), _get(derived, "rho_l"), _get(derived, "width"),
+                   [(nx / 2, ny / 2)], [radius])
+    x = np.arange(nx, dtype=np.float64)[None, :] * np.ones((ny, 1))
+    y = np.arange(ny, dtype=np.float64)[:, None] * np.ones((1, nx))
+    return rho, _f32(amplitude * np.sin(2 * np.pi * y / ny)), _f32(amplitude * np.sin(2 * np.pi * x / nx))
