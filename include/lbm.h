@@ -167,6 +167,24 @@ int lbm_step(lbm_ctx* ctx, int32_t n);
  * LBM_ENONFINITE if a total is not finite. */
 int lbm_moments(lbm_ctx* ctx, float* rho, float* ux, float* uy, double totals[3]);
 
+/* lbm_moments for callers that cannot allocate or synchronise (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same fields rho, ux, uy (device, each may be NULL) from the same
+ * kernel, and, if totals_dev is not NULL, the same FP64 totals written to
+ * `totals_dev`, a DEVICE array of 3 doubles, with no synchronisation (so no
+ * non-finite check: test the totals after the stream has finished); unlike
+ * the host `totals` of the other calls, totals_dev is device memory.  The
+ * call allocates nothing: the per-workgroup partial sums go to a fixed
+ * 2 MiB device array of the library (each device holds one until the
+ * process ends), which limits it to lattices of at most 87381 workgroups of
+ * 64 x 16 nodes (about 89M nodes; LBM_EINVAL beyond, before any launch).
+ * All contexts on one device share that array: calls that overlap on one
+ * device race, so issue them on one stream or order them.  Nothing carries
+ * over between calls (every partial is written before it is read).
+ * LBM_EHIP if the runtime gave no device address for the array at
+ * lbm_create. */
+int lbm_moments_noalloc(lbm_ctx* ctx, float* rho, float* ux, float* uy, double* totals_dev);
+
 /* ---- Checkpoints --------------------------------------------------------
  * A checkpoint is the library's own copy of the current state: the pull
  * buffer (lbm_state_bytes) followed, for the 2-byte storages, by the

@@ -30,6 +30,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 
@@ -1089,6 +1090,34 @@ RefPoly<float> make_refpoly(const lbm_derived& d, double a, double b, int storag
 }  // namespace
 }  // namespace lbm
 
+// Scratch of lbm_moments_noalloc: the per-workgroup FP64 partial sums of the
+// moments kernel, in a fixed device array instead of memory the library
+// allocates (callers that cannot allocate).  Every device holds its own copy
+// until the process ends; host code uses the device address taken by
+// hipGetSymbolAddress, never this name.  Calls on one device share it.
+constexpr size_t kNoallocScratchDoubles = 262144;  // 2 MiB: 87381 workgroups of 64 x 16 nodes
+static __device__ __align__(256) double scratch[kNoallocScratchDoubles];
+
+namespace lbm {
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices];  // address of `scratch` on each device, once taken
+
+// Address of the static scratch on `device`, which must be the current
+// device; taken once per device.  nullptr if the runtime cannot give it.
+double* noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch_dev[device] = static_cast<double*>(p);
+  }
+  return g_scratch_dev[device];
+}
+}  // namespace
+}  // namespace lbm
+
 using namespace lbm;
 
 struct lbm_ctx {
@@ -1109,6 +1138,7 @@ struct lbm_ctx {
   int* flag;
   int adj_blocks;    // workgroups of the adjoint tile grid
   double* theta;     // adj_blocks*3 accumulated partials of dL/dtheta, then 3 totals
+  double* noalloc;   // the static scratch on this device (lbm_moments_noalloc), or nullptr
 };
 
 namespace {
@@ -1286,6 +1316,7 @@ int lbm_create(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, void* r
   }
   c->flag = reinterpret_cast<int*>(c->scratch + 3 * (size_t)c->nblocks + 3);
   c->theta = c->scratch + mom_doubles;
+  c->noalloc = noalloc_scratch(c->device);  // c->device is current here
   *out = c;
   return LBM_OK;
 }
@@ -1415,6 +1446,24 @@ int lbm_moments(lbm_ctx* ctx, float* rho, float* ux, float* uy, double totals[3]
   HIP_OK(hipStreamSynchronize(ctx->stream));
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(totals[k])) return fail(LBM_ENONFINITE, "non-finite total (%d): the state has diverged", k);
+  return LBM_OK;
+}
+
+int lbm_moments_noalloc(lbm_ctx* ctx, float* rho, float* ux, float* uy, double* totals_dev) {
+  if (!ctx) return fail(LBM_EINVAL, "context is NULL");
+  if (3 * (size_t)ctx->nblocks > kNoallocScratchDoubles)
+    return fail(LBM_EINVAL,
+                "lbm_moments_noalloc: a %d x %d lattice needs %zu doubles of scratch, the static maximum is %zu "
+                "(%zu workgroups of 64 x 16 nodes); use lbm_moments",
+                ctx->p.nx, ctx->p.ny, 3 * (size_t)ctx->nblocks, kNoallocScratchDoubles, kNoallocScratchDoubles / 3);
+  if (int st = check_ctx(ctx, true)) return st;
+  if (!ctx->noalloc) return fail(LBM_EHIP, "lbm_moments_noalloc: the static scratch has no device address");
+  if (int st = set_device(ctx)) return st;
+  if (int st = launch_moments(ctx, rho, ux, uy, ctx->noalloc)) return st;
+  if (totals_dev) {
+    finish_sums<<<1, RED, 0, ctx->stream>>>(ctx->noalloc, ctx->nblocks, totals_dev);
+    HIP_OK(hipGetLastError());
+  }
   return LBM_OK;
 }
 

@@ -62,6 +62,7 @@ def _load():
         "lbm_get_state": (I, [V, V]),
         "lbm_step": (I, [V, ctypes.c_int32]),
         "lbm_moments": (I, [V, V, V, V, P(D)]),
+        "lbm_moments_noalloc": (I, [V, V, V, V, V]),
         "lbm_checkpoint_bytes": (ctypes.c_size_t, [P(lbm_params)]),
         "lbm_save_state": (I, [V, V]),
         "lbm_load_state": (I, [V, V, ctypes.c_int64]),
@@ -89,7 +90,7 @@ def _load():
 _lib = _load()
 EXPORTED = ("lbm_last_error", "lbm_derive", "lbm_sigma_paper", "lbm_state_bytes", "lbm_ref_bytes",
             "lbm_create", "lbm_set_stream", "lbm_init", "lbm_set_state", "lbm_get_state", "lbm_step",
-            "lbm_moments", "lbm_checkpoint_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_saved", "lbm_step_saved_chain", "lbm_adjoint_run",
+            "lbm_moments", "lbm_moments_noalloc", "lbm_checkpoint_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_saved", "lbm_step_saved_chain", "lbm_adjoint_run",
             "lbm_adjoint_bytes", "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_get", "lbm_adjoint_init",
             "lbm_adjoint_theta", "lbm_param_jacobian", "lbm_time", "lbm_get_derived", "lbm_destroy")
 
@@ -192,6 +193,13 @@ def lbm_moments(ctx, rho=None, ux=None, uy=None, totals=True, n=None):
     _check(_lib.lbm_moments(ctx, _ptr(rho, torch.float32, n, "rho"), _ptr(ux, torch.float32, n, "ux"),
                             _ptr(uy, torch.float32, n, "uy"), tot if totals else None))
     return tuple(tot) if totals else None
+
+
+def lbm_moments_noalloc(ctx, rho=None, ux=None, uy=None, totals_dev=None, n=None):
+    """lbm_moments without allocation or synchronisation: totals_dev, if given,
+    is a device float64 tensor of 3 elements written on the stream."""
+    _check(_lib.lbm_moments_noalloc(ctx, _ptr(rho, torch.float32, n, "rho"), _ptr(ux, torch.float32, n, "ux"),
+                                    _ptr(uy, torch.float32, n, "uy"), _ptr(totals_dev, torch.float64, 3, "totals_dev")))
 
 
 def lbm_checkpoint_bytes(params: lbm_params) -> int:
