@@ -25,7 +25,9 @@ Prints one JSON line:
                      against exact oracle derivatives stored in tests/golden;
   legs.fwd_adjoint_keep_all_states  the same crop keeping all 1000 states
                      in HBM (151 GB), so the backward recomputes nothing;
-  legs.coalescence_16384x8192  the step on the largest workload, each storage;
+  legs.coalescence_16384x8192  the step on the largest workload over its
+                     5000 steps, each storage, with the t = 5000 read-outs of
+                     the 2-byte runs against FP32;
   legs.elliptic_droplet  oscillation period of the paper's elliptic droplet
                      against the linear capillary mode;
   legs.head_on_collision  liquid bodies over time in head-on collisions of
@@ -162,18 +164,53 @@ def step_leg(pkg, wl, timer, storage, n, steps, warmup, tr=0.7, width=10.0):
                      "traffic": measured_traffic(kernel, n * n), "alu": alu_roofline(kernel, n * n, mlups)}
 
 
-def coalescence_leg(pkg, wl, timer, storage, nx=16384, ny=8192, steps=200, warmup=20):
+def _semi_axis(profile, level):
+    """Half the distance between the outer level crossings of a 1-D profile."""
+    i = np.where(profile > level)[0]
+    a, b = i.min(), i.max()
+    lo = a - (profile[a] - level) / (profile[a] - profile[a - 1])
+    hi = b + (profile[b] - level) / (profile[b] - profile[b + 1])
+    return 0.5 * (hi - lo)
+
+
+def coalescence_legs(pkg, wl, timer, nx=16384, ny=8192, steps=5000, warmup=20):
     """The largest workload: two R = 400 droplets 20 nodes apart on
-    16384 x 8192 at T/T_c = 0.6 (9.7 GB of FP32 A/B buffers)."""
+    16384 x 8192 at T/T_c = 0.6 (9.7 GB of FP32 A/B buffers), its 5000 steps
+    timed per storage, then the read-outs at t = 5000 of each 2-byte run
+    against the FP32 run: field max |d rho| / rho_l, gap density, liquid
+    bodies, the droplets' vertical semi-axes, liquid and gas densities."""
+    from scipy import ndimage
+    import torch
     d = pkg.lbm_derive(pkg.make_params(nx, ny, tr=0.6, width=10.0))
     rho0 = wl.coalescence({"rho_g": d.rho_g, "rho_l": d.rho_l, "width": 10.0}, nx, ny)
-    lat = pkg.Lattice(nx, ny, tr=0.6, width=10.0, storage=storage).init(rho0)
-    ms = timer(lambda: lat.step(steps), pre=lambda: lat.step(warmup))
-    lat.close()
-    per = ms / steps
-    gbs = BYTES_PER_LU[storage] * nx * ny / (per * 1e-3) / 1e9
-    return {"mlups": round(nx * ny * steps / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(per, 4),
-            "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    level = 0.5 * (d.rho_l + d.rho_g)
+    cx, cy = nx // 2, ny // 2
+    out, ref = {}, None
+    for storage in ("fp32", "fp16", "bf16"):
+        lat = pkg.Lattice(nx, ny, tr=0.6, width=10.0, storage=storage).init(rho0)
+        ms = timer(lambda: lat.step(steps), pre=lambda: lat.step(warmup))
+        rho = lat.moments()[0]
+        lat.close()
+        per = ms / steps
+        gbs = BYTES_PER_LU[storage] * nx * ny / (per * 1e-3) / 1e9
+        region = rho[cy - 600:cy + 600, cx - 1100:cx + 1100].double().cpu().numpy()
+        lab, count = ndimage.label(region > level)
+        sizes = ndimage.sum(np.ones_like(region), lab, range(1, count + 1))
+        leg = {"mlups": round(nx * ny * steps / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(per, 4),
+               "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4), "steps_timed": steps,
+               "t5000": {"gap_density": float(rho[cy, cx]), "liquid_bodies": int(np.sum(np.asarray(sizes) > 20)),
+                         "semi_axes": [round(_semi_axis(rho[:, x].double().cpu().numpy(), level), 4)
+                                       for x in (cx - 410, cx + 410)],
+                         "liquid_density": [float(rho[cy, x]) for x in (cx - 410, cx + 410)],
+                         "gas_density": float(rho[0, 0])}}
+        if ref is None:
+            ref = rho
+        else:
+            leg["t5000"]["max_drho_vs_fp32_rel_rho_l"] = float((rho - ref).abs().max().item() / d.rho_l)
+            del rho
+        out[storage] = leg
+        torch.cuda.empty_cache()
+    return out
 
 
 def ellipse_leg(pkg, wl, n=512, tr=0.6, width=10.0, s_p=1.4, every=100, nsamp=600):
@@ -418,7 +455,7 @@ def main():
             leg["coexistence"] = coexistence_leg(pkg, wl, st)
             legs[st] = leg
         legs["fp32_coexistence"] = coexistence_leg(pkg, wl, "fp32")
-        legs["coalescence_16384x8192"] = {st: coalescence_leg(pkg, wl, timer, st) for st in ("fp32", "fp16", "bf16")}
+        legs["coalescence_16384x8192"] = coalescence_legs(pkg, wl, timer)
         legs["elliptic_droplet"] = ellipse_leg(pkg, wl)
         legs["head_on_collision"] = head_on_leg(pkg, wl)
         legs["fwd_adjoint"] = fwd_adjoint_leg(pkg, wl, timer, torch)

@@ -20,13 +20,15 @@ STORAGES = ["fp16", "bf16"]
 # one rounding of a deviation of ~1e-3 rho per step is ~2^-12 (FP16) or
 # ~2^-9 (BF16) of it; the bounds leave a factor ~5 over what the run shows.
 STEP_TOL = {"fp16": 1e-4, "bf16": 1e-3}
-# Coexistence densities of the 2-byte runs against the FP32 run, / rho_l.  A
-# relaxed interface repeats the same roundings every step, so the storage
-# leaves a steady offset rather than noise, and its size follows the exact
-# rounding pattern: for FP16 it measured 0.6e-4 to 1.5e-4 over arithmetic
-# variants of the same kernel.  FP16 is held to 4e-4 (a quarter of the 1e-3
-# gate); BF16, with 3 significand bits fewer, only to the gate.
-COEX_VS_FP32 = {"fp16": 4e-4, "bf16": 1e-3}
+# Coexistence densities of the 2-byte runs against the FP32 run, / rho_l:
+# the storage's coexistence bound (1e-3 of rho_l) applies to both.  A relaxed
+# interface repeats the same roundings every step, so the storage leaves a
+# steady offset rather than noise; its size is set by how those persistent
+# roundings balance between interface and bulk and follows the exact
+# rounding pattern, not the significand alone (FP16: 0.6e-4 to 1.5e-4, BF16:
+# 0.8e-4 to 4.3e-4 over arithmetic variants of the kernel and three fits of
+# the reference), so no tighter bound is derived.
+COEX_VS_FP32 = {"fp16": 1e-3, "bf16": 1e-3}
 
 
 def droplet(n=96, tr=0.7):
@@ -99,6 +101,8 @@ def test_coexistence_error(storage):
     if storage != "fp32":
         g32, l32 = run("fp32")
         tol = COEX_VS_FP32[storage]
+        print(f"{storage}: rho_l - rho_l(fp32) = {(l - l32) / co.rho_l:+.2e} rho_l, "
+              f"rho_g - rho_g(fp32) = {(g - g32) / co.rho_l:+.2e} rho_l")
         assert abs(l - l32) / co.rho_l <= tol and abs(g - g32) / co.rho_l <= tol, (l - l32, g - g32)
 
 
@@ -191,3 +195,101 @@ def test_sampled_parity_largest_lattice(storage):
     del st
     lat.close()
     assert np.abs(got - ref).max() / co.rho_l <= STEP_TOL[storage]
+
+
+@pytest.mark.parametrize("storage", STORAGES)
+def test_window_parity_spinodal_4096(storage):
+    """The 4096^2 spinodal workload in 2-byte storage over its 2000 steps:
+    at t0 = 0, 500, 1000, 1500 and 1900 the decoded GPU state on a
+    light-cone crop (half-width 2 x 100 + 3) runs 100 FP64 oracle steps and
+    the 5 x 5 nodes around the crop's centre are compared with the GPU's own
+    next 100 steps, within the storage bound STEP_TOL: the error is the
+    storage's rounding over the window, from developed interfaces as well
+    as the initial noise."""
+    from tests._gpu_helpers import crop_periodic
+    n, window = 4096, 100
+    _, co = params_pair(n, n, tr=0.7, width=10.0)
+    lat = lattice(n, n, wl.spinodal(co, n=n), tr=0.7, width=10.0, storage=storage)
+    half = 2 * window + 3
+    centres = {0: [(2047, 2048)], 500: [(1500, 2600), (4095, 0)], 1000: [(3000, 700)], 1500: [(9, 2222)],
+               1900: [(300, 3333)]}
+    for t0 in sorted(centres):
+        lat.step(t0 - lat.time)
+        st = lat.state()
+        crops = [crop_periodic(st, cx, cy, half).double().cpu().numpy() for cx, cy in centres[t0]]
+        del st
+        lat.step(window)
+        st = lat.state()
+        for (cx, cy), crop in zip(centres[t0], crops):
+            with np.errstate(over="ignore", invalid="ignore", divide="ignore"):  # crop seam, outside the light cone
+                ref = lbm.run(crop, co, window, lbm.collide_sequence)[:, half - 2:half + 3, half - 2:half + 3]
+            assert np.all(np.isfinite(ref))
+            got = crop_periodic(st, cx, cy, 2).double().cpu().numpy()
+            err = np.abs(got.sum(0) - ref.sum(0)).max() / co.rho_l
+            print(f"{storage} t0 = {t0} ({cx}, {cy}): max |d rho| / rho_l = {err:.2e}")
+            assert err <= STEP_TOL[storage], (t0, cx, cy, err)
+        del st
+
+
+def _semi_axis(profile, level):
+    """Half the distance between the outer level crossings of a 1-D density
+    profile, linearly interpolated."""
+    i = np.where(profile > level)[0]
+    a, b = i.min(), i.max()
+    lo = a - (profile[a] - level) / (profile[a] - profile[a - 1])
+    hi = b + (profile[b] - level) / (profile[b] - profile[b + 1])
+    return 0.5 * (hi - lo)
+
+
+def coalescence_statistics(rho, co, nx, ny):
+    """Read-outs of the droplet pair (R = 400, centres nx/2 -+ 410) from a
+    device density field: gap density at the midpoint, liquid bodies in the
+    region around the pair, each droplet's vertical semi-axis through its
+    centre, liquid density at the centres, gas density far from the pair."""
+    from scipy import ndimage
+    level = 0.5 * (co.rho_l + co.rho_g)
+    cx, cy = nx // 2, ny // 2
+    region = rho[cy - 600:cy + 600, cx - 1100:cx + 1100].double().cpu().numpy()
+    lab, count = ndimage.label(region > level)
+    sizes = ndimage.sum(np.ones_like(region), lab, range(1, count + 1))
+    centres = (cx - 410, cx + 410)
+    return {"gap": float(rho[cy, cx]), "bodies": int(np.sum(np.asarray(sizes) > 20)),
+            "semi_axes": [_semi_axis(rho[:, x].double().cpu().numpy(), level) for x in centres],
+            "liquid": [float(rho[cy, x]) for x in centres], "gas": float(rho[0, 0])}
+
+
+def test_coalescence_5000_steps_against_fp32():
+    """The 16384 x 8192 droplet pair (R = 400, gap 20, T_r = 0.6, density
+    ratio 132) over its 5000 steps in FP32, FP16 and BF16.  Against the FP32
+    run: the bulk liquid and gas densities within the coexistence bound
+    (1e-3 rho_l), the gap density within it too, the same number of liquid
+    bodies, each droplet's semi-axis within half a lattice spacing (the
+    storage may shift a curved interface but not by a node), and for FP16
+    the whole field within 1e-3 rho_l.  The BF16 field difference is
+    reported: it is the interface shift times the interface's density slope
+    (up to 0.06 rho per node), not a bulk error."""
+    nx, ny, steps = 16384, 8192, 5000
+    _, co = params_pair(nx, ny, tr=0.6, width=10.0)
+    rho0 = wl.coalescence(co, nx, ny)
+    ref, stats = None, {}
+    for storage in ["fp32"] + STORAGES:
+        lat = lattice(nx, ny, rho0, tr=0.6, width=10.0, storage=storage).step(steps)
+        rho = lat.moments()[0]
+        lat.close()
+        del lat
+        stats[storage] = coalescence_statistics(rho, co, nx, ny)
+        if ref is None:
+            ref = rho
+            continue
+        field = (rho - ref).abs().max().item() / co.rho_l
+        s, r = stats[storage], stats["fp32"]
+        print(f"{storage}: max |d rho| / rho_l {field:.2e}, gap {s['gap']:.6f} (fp32 {r['gap']:.6f}), "
+              f"bodies {s['bodies']}, semi-axes {np.round(s['semi_axes'], 3)} (fp32 {np.round(r['semi_axes'], 3)})")
+        assert s["bodies"] == r["bodies"] == 2
+        assert abs(s["gap"] - r["gap"]) <= 1e-3 * co.rho_l
+        assert abs(s["gas"] - r["gas"]) <= 1e-3 * co.rho_l
+        assert max(abs(a - b) for a, b in zip(s["liquid"], r["liquid"])) <= 1e-3 * co.rho_l
+        assert max(abs(a - b) for a, b in zip(s["semi_axes"], r["semi_axes"])) <= 0.5
+        if storage == "fp16":
+            assert field <= 1e-3, field
+        del rho
