@@ -20,12 +20,12 @@
  *  - Field and buffer pointers (f, f_*, rho*, u*, lam, adj*, drho0, src,
  *    dst) are DEVICE pointers owned by the caller (any allocator; the
  *    library never frees them).  The result pointers out, sigma_out,
- *    totals, dtheta, jac and which, and the pointer arrays bufs and
+ *    totals, dtheta, dparams, jac and which, and the pointer arrays bufs and
  *    f_states (whose elements are device pointers), are HOST pointers.
  *  - Every call is asynchronous on the stream given to lbm_create (or
  *    lbm_set_stream), except where stated: lbm_init, lbm_moments (with
- *    totals) and lbm_adjoint_theta (with dtheta) synchronise that stream to
- *    return host results.
+ *    totals), lbm_adjoint_theta (with dtheta) and lbm_adjoint_params
+ *    synchronise that stream to return host results.
  *  - Every int-returning call returns LBM_OK (0) or a negative status;
  *    lbm_last_error() then returns a message for the calling thread.  A
  *    failed call launches nothing and leaves the state unchanged, except
@@ -139,7 +139,8 @@ size_t lbm_ref_bytes(const lbm_params* p);
 int lbm_create(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b,
                void* rho_ref, void* stream);
 
-/* Change the stream used by later calls. */
+/* Change the stream used by later calls.  Work already queued on the old
+ * stream is ordered before anything later calls queue on the new one. */
 int lbm_set_stream(lbm_ctx* ctx, void* stream);
 
 /* Initial state f_i = (M^-1 m^eq(rho0, u0, eta(rho0)))_i at t = 0 (main
@@ -268,6 +269,15 @@ int lbm_adjoint_init(lbm_ctx* ctx, const float* rho0, const float* ux0, const fl
  * (synchronises the stream); then clear the accumulator if reset != 0.
  * LBM_ENONFINITE if a component is not finite. */
 int lbm_adjoint_theta(lbm_ctx* ctx, double dtheta[3], int32_t reset);
+
+/* dL/d(sigma, W, T_r) of the accumulated adjoint: dparams[j] =
+ * sum_k jac[3*k + j] dL/dtheta_k with jac = lbm_param_jacobian at the
+ * context's parameters (the chain rule through theta = (G'^2, K', R T) of
+ * main Eqs. 20, 21, 23).  Reads the accumulator like lbm_adjoint_theta
+ * (synchronises the stream) and clears it if reset != 0; dparams (host, 3)
+ * receives the three derivatives, dtheta (host, 3, may be NULL) dL/dtheta.
+ * LBM_ENONFINITE if a component is not finite. */
+int lbm_adjoint_params(lbm_ctx* ctx, double dparams[3], double dtheta[3], int32_t reset);
 
 /* Host-only: jac[3*k + j] = d theta_k / d (sigma, W, T_r)_j at the point of
  * *p (main Eqs. 20, 21, 23), with sigma the value lbm_derive reports, held

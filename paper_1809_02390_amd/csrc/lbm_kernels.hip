@@ -1328,7 +1328,18 @@ int lbm_create(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, void* r
 
 int lbm_set_stream(lbm_ctx* ctx, void* stream) {
   if (int st = check_ctx(ctx, false)) return st;
-  ctx->stream = (hipStream_t)stream;
+  const hipStream_t next = (hipStream_t)stream;
+  if (next != ctx->stream) {
+    // work queued on the old stream precedes everything issued on the new one
+    if (int st = set_device(ctx)) return st;
+    hipEvent_t ev;
+    HIP_OK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(ev, ctx->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(next, ev, 0);
+    (void)hipEventDestroy(ev);  // released once the wait has been satisfied
+    if (e != hipSuccess) return fail(LBM_EHIP, "lbm_set_stream: %s", hipGetErrorString(e));
+  }
+  ctx->stream = next;
   return LBM_OK;
 }
 
@@ -1643,6 +1654,18 @@ int lbm_adjoint_theta(lbm_ctx* ctx, double dtheta[3], int32_t reset) {
     for (int k = 0; k < 3; ++k)
       if (!std::isfinite(dtheta[k])) return fail(LBM_ENONFINITE, "non-finite parameter gradient (%d)", k);
   }
+  return LBM_OK;
+}
+
+int lbm_adjoint_params(lbm_ctx* ctx, double dparams[3], double dtheta[3], int32_t reset) {
+  if (!dparams) return fail(LBM_EINVAL, "dparams is NULL");
+  double th[3];
+  if (int st = lbm_adjoint_theta(ctx, th, reset)) return st;
+  double jac[9];
+  if (int st = lbm::param_jacobian(&ctx->p, jac, g_err, sizeof g_err)) return st;
+  for (int j = 0; j < 3; ++j) dparams[j] = jac[j] * th[0] + jac[3 + j] * th[1] + jac[6 + j] * th[2];
+  if (dtheta)
+    for (int k = 0; k < 3; ++k) dtheta[k] = th[k];
   return LBM_OK;
 }
 

@@ -9,6 +9,7 @@ that want torch to own the memory.
 from __future__ import annotations
 
 import ctypes
+import functools
 import os
 
 import torch
@@ -75,6 +76,7 @@ def _load():
         "lbm_adjoint_get": (I, [V, V, V]),
         "lbm_adjoint_init": (I, [V, V, V, V, V, V]),
         "lbm_adjoint_theta": (I, [V, P(D), ctypes.c_int32]),
+        "lbm_adjoint_params": (I, [V, P(D), P(D), ctypes.c_int32]),
         "lbm_param_jacobian": (I, [P(lbm_params), P(D)]),
         "lbm_time": (ctypes.c_int64, [V]),
         "lbm_get_derived": (I, [V, P(lbm_derived)]),
@@ -92,7 +94,7 @@ EXPORTED = ("lbm_last_error", "lbm_derive", "lbm_sigma_paper", "lbm_state_bytes"
             "lbm_create", "lbm_set_stream", "lbm_init", "lbm_set_state", "lbm_get_state", "lbm_step",
             "lbm_moments", "lbm_moments_noalloc", "lbm_checkpoint_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_saved", "lbm_step_saved_chain", "lbm_adjoint_run",
             "lbm_adjoint_bytes", "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_get", "lbm_adjoint_init",
-            "lbm_adjoint_theta", "lbm_param_jacobian", "lbm_time", "lbm_get_derived", "lbm_destroy")
+            "lbm_adjoint_theta", "lbm_adjoint_params", "lbm_param_jacobian", "lbm_time", "lbm_get_derived", "lbm_destroy")
 
 
 def _check(status: int):
@@ -278,6 +280,14 @@ def lbm_adjoint_theta(ctx, read=True, reset=True):
     return tuple(out) if read else None
 
 
+def lbm_adjoint_params(ctx, reset=True):
+    """(dL/d(sigma, W, T_r), dL/d theta) of the accumulated adjoint, each a
+    3-tuple; the chain rule is applied by the library."""
+    dp, dth = (ctypes.c_double * 3)(), (ctypes.c_double * 3)()
+    _check(_lib.lbm_adjoint_params(ctx, dp, dth, 1 if reset else 0))
+    return tuple(dp), tuple(dth)
+
+
 def lbm_param_jacobian(params: lbm_params):
     """d(G'^2, K', RT)/d(sigma, W, T_r) as a 3 x 3 nested list (rows: theta)."""
     out = (ctypes.c_double * 9)()
@@ -302,8 +312,32 @@ def lbm_destroy(ctx):
 # ---------------------------------------------------------------------------
 # Convenience owner of buffers + context
 # ---------------------------------------------------------------------------
+def _ordered(method):
+    """Run a Lattice method with its context stream ordered after torch's
+    current stream (the caller's earlier work on the tensors it passes) and
+    torch's current stream ordered after the context stream (the caller's
+    later use of results, and the caching allocator's reuse of tensors the
+    library still reads or writes).  Nothing to do when they are the same."""
+    @functools.wraps(method)
+    def run(self, *args, **kw):
+        cur = torch.cuda.current_stream(self.f_a.device)
+        if cur == self.stream:
+            return method(self, *args, **kw)
+        self.stream.wait_stream(cur)
+        try:
+            return method(self, *args, **kw)
+        finally:
+            cur.wait_stream(self.stream)
+    return run
+
+
 class Lattice:
-    """Torch-owned A/B buffers plus a library context on the current device."""
+    """Torch-owned A/B buffers plus a library context on the current device.
+
+    The context launches on `stream` (torch's current stream at creation if
+    None); every method orders that stream with torch's current stream at
+    the call, so tensors passed in and returned follow torch's stream
+    semantics."""
 
     def __init__(self, nx, ny, device="cuda", stream=None, **kw):
         self.params = make_params(nx, ny, **kw)
@@ -315,9 +349,13 @@ class Lattice:
         self.f_b = torch.empty(nbytes, dtype=torch.uint8, device=device)
         rb = lbm_ref_bytes(self.params)
         self.rho_ref = torch.empty(rb, dtype=torch.uint8, device=device) if rb else None
-        self.ctx = lbm_create(self.params, self.f_a, self.f_b, self.rho_ref, stream)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.f_a.device)
+        if stream is not None:
+            self.stream.wait_stream(torch.cuda.current_stream(self.f_a.device))  # buffers allocated above
+        self.ctx = lbm_create(self.params, self.f_a, self.f_b, self.rho_ref, self.stream)
         self.derived = lbm_get_derived(self.ctx)
 
+    @_ordered
     def init(self, rho0, ux0=None, uy0=None):
         dev = self.f_a.device
         conv = lambda a: None if a is None else torch.as_tensor(a, dtype=torch.float32).to(dev).contiguous()
@@ -325,21 +363,25 @@ class Lattice:
         lbm_init(self.ctx, *self._keep, n=self.n)
         return self
 
+    @_ordered
     def set_state(self, f):
         f = torch.as_tensor(f, dtype=torch.float32).to(self.f_a.device).contiguous()
         lbm_set_state(self.ctx, f, n=self.n)
         self._keep = [f]
         return self
 
+    @_ordered
     def state(self):
         f = torch.empty((9, self.ny, self.nx), dtype=torch.float32, device=self.f_a.device)
         lbm_get_state(self.ctx, f, n=self.n)
         return f
 
+    @_ordered
     def step(self, n=1):
         lbm_step(self.ctx, n)
         return self
 
+    @_ordered
     def moments(self, fields=True):
         dev = self.f_a.device
         if fields:
@@ -352,16 +394,19 @@ class Lattice:
     def checkpoint_buffer(self):
         return torch.empty(lbm_checkpoint_bytes(self.params), dtype=torch.uint8, device=self.f_a.device)
 
+    @_ordered
     def save_state(self, dst=None):
         dst = self.checkpoint_buffer() if dst is None else dst
         lbm_save_state(self.ctx, dst, lbm_checkpoint_bytes(self.params))
         return dst
 
+    @_ordered
     def load_state(self, src, t=0):
         lbm_load_state(self.ctx, src, t, lbm_checkpoint_bytes(self.params))
         self._keep = [src]
         return self
 
+    @_ordered
     def step_saved(self, src, dst):
         lbm_step_saved(self.ctx, src, dst, lbm_checkpoint_bytes(self.params))
         return dst
@@ -373,31 +418,37 @@ class Lattice:
             raise LbmError(LBM_EINVAL, "the adjoint needs LBM_FP32 storage")
         return torch.empty(nbytes, dtype=torch.uint8, device=self.f_a.device)
 
+    @_ordered
     def adjoint_seed(self, lam, adj=None):
         adj = self.adjoint_buffer() if adj is None else adj
         lam = torch.as_tensor(lam, dtype=torch.float32).to(self.f_a.device).contiguous()
         lbm_adjoint_seed(self.ctx, lam, adj, self.n, lbm_adjoint_bytes(self.params))
         return adj
 
+    @_ordered
     def adjoint_step(self, f_t, adj_next, adj_out):
         lbm_adjoint_step(self.ctx, f_t, adj_next, adj_out, lbm_checkpoint_bytes(self.params),
                          lbm_adjoint_bytes(self.params))
         return adj_out
 
+    @_ordered
     def step_saved_chain(self, bufs):
         lbm_step_saved_chain(self.ctx, bufs, lbm_checkpoint_bytes(self.params))
 
+    @_ordered
     def adjoint_run(self, f_states, adj_a, adj_b):
         """Adjoint steps back through f_states; returns the buffer holding the result."""
         w = lbm_adjoint_run(self.ctx, f_states, adj_a, adj_b, lbm_checkpoint_bytes(self.params),
                             lbm_adjoint_bytes(self.params))
         return adj_a if w == 0 else adj_b
 
+    @_ordered
     def adjoint_get(self, adj):
         lam = torch.empty((9, self.ny, self.nx), dtype=torch.float32, device=self.f_a.device)
         lbm_adjoint_get(self.ctx, adj, lam, self.n, lbm_adjoint_bytes(self.params))
         return lam
 
+    @_ordered
     def adjoint_init(self, rho0, adj0, ux0=None, uy0=None):
         dev = self.f_a.device
         conv = lambda a: None if a is None else torch.as_tensor(a, dtype=torch.float32).to(dev).contiguous()
@@ -406,6 +457,7 @@ class Lattice:
         lbm_adjoint_init(self.ctx, rho0, ux0, uy0, adj0, drho0, self.n, lbm_adjoint_bytes(self.params))
         return drho0
 
+    @_ordered
     def adjoint_theta(self, reset=True):
         return lbm_adjoint_theta(self.ctx, True, reset)
 

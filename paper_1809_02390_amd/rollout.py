@@ -16,7 +16,9 @@ first, the segment's states are recomputed from its checkpoint (bit for bit
 the forward's) and the adjoint steps run back through them
 (lbm_adjoint_run); lbm_adjoint_init closes with dL/d rho0, and
 
-    dL/d(sigma, W, T_r) = J^T dL/d theta,   J = lbm_param_jacobian.
+    dL/d(sigma, W, T_r) = J^T dL/d theta,   J = lbm_param_jacobian,
+
+applied by the library (lbm_adjoint_params).
 
 Device memory: ceil(n / every) + 1 checkpoints + (every - 1) segment states
 + two adjoint states (11 fields each), all FP32 over nx*ny nodes.  With
@@ -35,7 +37,7 @@ import math
 
 import torch
 
-from .lbm import Lattice, lbm_adjoint_bytes, lbm_adjoint_theta, lbm_checkpoint_bytes, lbm_param_jacobian
+from .lbm import Lattice, lbm_adjoint_bytes, lbm_adjoint_params, lbm_adjoint_theta, lbm_checkpoint_bytes
 
 
 def rollout_bytes(nsteps, every, state_bytes, adjoint_bytes):
@@ -141,9 +143,7 @@ class Rollout:
         adj0 = self.backward_state(g.expand(9, self.ny, self.nx).contiguous())
         rho0, ux0, uy0 = self.inputs
         drho0 = self.lat.adjoint_init(rho0, adj0, ux0, uy0)
-        dth = self.lat.adjoint_theta(reset=True)
-        J = lbm_param_jacobian(self.lat.params)
-        dp = tuple(sum(J[k][j] * dth[k] for k in range(3)) for j in range(3))
+        dp, dth = lbm_adjoint_params(self.lat.ctx, reset=True)
         return drho0, dth, dp
 
     def release(self):

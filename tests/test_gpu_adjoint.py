@@ -91,6 +91,24 @@ def test_adjoint_step_matches_oracle(case):
     assert np.all(np.abs(dth - ref_th) <= 1e-5 * scale), (dth, ref_th, scale)
 
 
+def test_adjoint_params_apply_the_parameter_jacobian(case):
+    """lbm_adjoint_params returns dL/d(sigma, W, T_r) = J^T dL/dtheta with
+    J = lbm_param_jacobian at the context's parameters, from the same
+    accumulator as lbm_adjoint_theta, and clears it on request."""
+    nx, ny, co, f, lam = case
+    lat = pkg.Lattice(nx, ny, tr=0.7, width=5.0).set_state(f)
+    ck = lat.save_state()
+    a, b = lat.adjoint_seed(lam), lat.adjoint_buffer()
+    lat.adjoint_theta(reset=True)
+    lat.adjoint_step(ck, a, b)
+    dth = np.array(lat.adjoint_theta(reset=False))
+    dp, dth2 = pkg.lbm.lbm_adjoint_params(lat.ctx, reset=True)
+    assert np.array_equal(np.array(dth2), dth)
+    J = np.array(pkg.lbm_param_jacobian(lat.params))
+    np.testing.assert_allclose(np.array(dp), J.T @ dth, rtol=1e-12, atol=0)
+    assert lat.adjoint_theta(reset=True) == (0.0, 0.0, 0.0)
+
+
 @pytest.mark.parametrize("nx,ny", [(4096, 4096), (16384, 8192)])
 def test_adjoint_step_sampled(nx, ny):
     """One adjoint step on a spinodal field (mean of the coexistence

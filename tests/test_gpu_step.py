@@ -351,16 +351,45 @@ def test_two_lattices_on_two_streams_match_single_runs():
     assert torch.equal(got[0], ref_a) and torch.equal(got[1], ref_b)
 
 
+def test_side_stream_results_follow_torch_stream_order():
+    """A lattice on a side stream, used from torch's current stream with no
+    explicit synchronisation: every call orders its stream after the
+    current one and the current one after it, so results read on the
+    current stream are complete, and tensors freed on it are not reused
+    while the library still reads them."""
+    nx, ny = 600, 400
+    _, co = params_pair(nx, ny, tr=0.7, width=10.0)
+    rho = wl.droplets(nx, ny, co.rho_g, co.rho_l, co.width, [(300, 200)], [60.0])
+    ref = lattice(nx, ny, rho, tr=0.7, width=10.0).step(300)
+    ref_f, ref_rho = ref.state(), ref.moments()[0]
+    side = torch.cuda.Stream()
+    lat = pkg.Lattice(nx, ny, stream=side, tr=0.7, width=10.0)
+    rho_dev = torch.tensor(rho, dtype=torch.float32, device="cuda")  # written on the current stream
+    lat.init(rho_dev)
+    del rho_dev
+    lat.step(300)  # queued on the side stream
+    f = lat.state()  # read back on the current stream without synchronising
+    assert torch.equal(f, ref_f)
+    r, _, _, _ = lat.moments()
+    assert torch.equal(r, ref_rho)
+
+
 @pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
 def test_laplace_law_256(storage):
     """Static droplets R = 20..60 on 256^2 (T_r = 0.8, W = 10, sigma_paper),
-    relaxed for 80000 steps (the breathing mode has decayed by 60000): the
-    fitted slope of Delta p against 1/R over R >= 30 matches sigma within 3%,
-    each R >= 40 within 3%, R = 20 within 10% (W/R = 0.5).  Spurious currents
-    (no bound in the paper) must stay below 1e-3 in lattice units.  FP16
-    storage keeps every bound.  BF16 storage (8-bit significand) keeps them
-    for R >= 30; its R = 20 droplet dissolves further (radius about 13 against
-    about 15 in FP32), so there it must only survive, with its ratio reported."""
+    relaxed for 80000 steps (the breathing mode has decayed by 60000).  The
+    slope of Delta p against 1/R fitted over R in {20..60} is reported; the
+    R = 20 droplet (W/R = 0.5) is mostly interface and its pressure jump
+    falls 8 % short of sigma/R in FP32 too, a finite-thickness effect of the
+    model (at W = 5 the same droplet is within 3 %:
+    test_laplace_small_droplet_thin_interface), so the gated fit is over
+    R >= 30: within 3 % of sigma, each R >= 40 within 3 %, R = 20 within 10 %.
+    Spurious currents (no bound in the paper) must stay below 1e-3 in
+    lattice units.  FP16 storage keeps every bound.  BF16 storage (8-bit
+    significand) keeps them for R >= 30; its R = 20 droplet ends between
+    radius 13 and 15.7 (FP32: 15.4) depending only on how its rounding falls
+    (three equally valid reference fits, same significand), so there it must
+    only survive, with its ratio reported."""
     n = 256
     _, co = params_pair(n, n, tr=0.8, width=10.0)
     inv_r, dps, report = [], [], []
@@ -371,12 +400,13 @@ def test_laplace_law_256(storage):
         r = r.double().cpu().numpy()
         sigma, radius, dp = measure.laplace_sigma(r, (n // 2, n // 2), co)
         umax = float(torch.hypot(ux, uy).max())
-        if R >= 30:
-            inv_r.append(1.0 / radius)
-            dps.append(dp)
+        inv_r.append(1.0 / radius)
+        dps.append(dp)
         report.append((R, round(radius, 3), round(sigma / co.sigma, 4), umax))
-    print(storage, "R, measured R, sigma/sigma_prescribed, max|u|:", report)
-    slope = np.polyfit(inv_r, dps, 1)[0]
+    slope_all = np.polyfit(inv_r, dps, 1)[0]
+    slope = np.polyfit(inv_r[1:], dps[1:], 1)[0]
+    print(storage, "R, measured R, sigma/sigma_prescribed, max|u|:", report,
+          f"slope / sigma: R 20..60 {slope_all / co.sigma:.4f}, R 30..60 {slope / co.sigma:.4f}")
     assert slope == pytest.approx(co.sigma, rel=0.03), (slope / co.sigma, report)
     for R, radius, ratio, umax in report:
         assert umax < 1e-3, report
@@ -384,6 +414,21 @@ def test_laplace_law_256(storage):
             assert radius > 10.0, report
             continue
         assert ratio == pytest.approx(1.0, abs=0.03 if R >= 40 else 0.10), report
+
+
+def test_laplace_small_droplet_thin_interface():
+    """The R = 20 droplet with a thinner interface, W = 5 (W/R = 0.25, the
+    ratio of the R = 40, W = 10 droplet): its pressure jump is within 3 % of
+    sigma/R, so the 8 % shortfall at W = 10 comes from W/R = 0.5, not from
+    the droplet's size on the lattice."""
+    n = 256
+    _, co = params_pair(n, n, tr=0.8, width=5.0)
+    lat = lattice(n, n, wl.static_droplet(co, n, 20.0), tr=0.8, width=5.0)
+    lat.step(80000)
+    r = lat.moments()[0].double().cpu().numpy()
+    sigma, radius, _ = measure.laplace_sigma(r, (n // 2, n // 2), co)
+    print(f"R = 20, W = 5: radius {radius:.3f}, sigma / sigma_prescribed {sigma / co.sigma:.4f}")
+    assert sigma / co.sigma == pytest.approx(1.0, abs=0.03)
 
 
 def test_coexistence_and_width_gpu():
