@@ -52,6 +52,8 @@ HBM_PEAK_GBS = 8000.0
 #   adjoint step: f(t) 9 + L 9 + force adjoint 2 read, L 9 + force adjoint 2 written (4 B each).
 BYTES_PER_LU = {"fp32": 72, "fp16": 40, "bf16": 40}
 ADJ_BYTES_PER_LU = 124
+# the same without the two force-adjoint planes: f(t) 9 + lambda 9 read, lambda 9 written
+ADJ_MIN_BYTES_PER_LU = 108
 # rocprofv3 FETCH_SIZE / WRITE_SIZE summaries of each kernel on the 4096^2 workload
 PROFILE_TRAFFIC = {k: os.path.join(ROOT, "profiles", f"traffic_{k}_spinodal4096.json")
                    for k in ("step_f32", "step_f16", "step_bf16", "adjoint_f32")}
@@ -348,9 +350,12 @@ def adjoint_kernel_leg(pkg, wl, timer, torch, n=4096, reps=200, tr=0.7, width=10
     if not np.all(np.isfinite(th)):
         raise RuntimeError("adjoint diverged")
     gbs = ADJ_BYTES_PER_LU * n * n / (ms * 1e-3) / 1e9
+    gbs_min = ADJ_MIN_BYTES_PER_LU * n * n / (ms * 1e-3) / 1e9
     return {"workload": f"spinodal decomposition {n}x{n}, T/Tc={tr}, W={width}", "ms_per_step": round(ms, 5),
             "mlups": round(n * n / (ms * 1e-3) / 1e6, 1), "achieved_gbs": round(gbs, 1),
             "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_lu": ADJ_BYTES_PER_LU,
+            "frac_on_lambda_and_state_bytes": round(gbs_min / HBM_PEAK_GBS, 4),
+            "lambda_and_state_bytes_per_lu": ADJ_MIN_BYTES_PER_LU,
             "traffic": measured_traffic("adjoint_f32", n * n),
             "alu": alu_roofline("adjoint_f32", n * n, n * n / (ms * 1e-3) / 1e6)}
 

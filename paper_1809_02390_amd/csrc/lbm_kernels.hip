@@ -754,20 +754,39 @@ struct AHalo {
   float v[R][2];
 };
 
+// Halo coordinates (hx, hy) of the entries p = tid, tid + NTHREADS, ... of
+// a W-wide row-major table, stepped without divisions: one division for the
+// first entry, then NTHREADS = DY W + DX per step.
+template <int W, int NTHREADS>
+struct HaloWalk {
+  static constexpr int DY = NTHREADS / W, DX = NTHREADS % W;
+  int hx, hy;
+  __device__ __forceinline__ explicit HaloWalk(int p) : hx(p % W), hy(p / W) {}
+  __device__ __forceinline__ void next() {
+    hx += DX;
+    hy += DY;
+    if (hx >= W) hx -= W, ++hy;
+  }
+};
+
+// 32-bit byte offsets from the A planes' bases: (y rp + x) 4 < 44 nx ny for
+// interleaved rows (44 nx ny < 2^32) and < 4 nx ny for planes.
 template <class S, bool kInterior = false>
 __device__ __forceinline__ void load_a(const float* __restrict__ ax, const float* __restrict__ ay, int nx, int ny,
                                        unsigned rp, int x0, int y0, AHalo<S>& h) {
   using L = AdjLds<S>;
   const int tid = threadIdx.y * S::TX + threadIdx.x;
+  HaloWalk<L::AW, S::NTHREADS> w(tid);
 #pragma unroll
   for (int r = 0; r < AHalo<S>::R; ++r) {
     const int p = tid + r * S::NTHREADS;
     if (p >= L::NA) break;
-    const int hx = p % L::AW, hy = p / L::AW;
-    const size_t o = kInterior ? (size_t)(y0 + hy - 2) * rp + (x0 + hx - 2)
-                               : (size_t)wrap(y0 + hy - 2, ny) * rp + wrap(x0 + hx - 2, nx);
-    h.v[r][0] = ax[o];
-    h.v[r][1] = ay[o];
+    const unsigned yy = kInterior ? (unsigned)(y0 + w.hy - 2) : (unsigned)wrap(y0 + w.hy - 2, ny);
+    const unsigned xx = kInterior ? (unsigned)(x0 + w.hx - 2) : (unsigned)wrap(x0 + w.hx - 2, nx);
+    const unsigned off = 4u * (yy * rp + xx);
+    h.v[r][0] = ldb<float>(reinterpret_cast<const char*>(ax), off);
+    h.v[r][1] = ldb<float>(reinterpret_cast<const char*>(ay), off);
+    w.next();
   }
 }
 
@@ -788,8 +807,9 @@ __device__ __forceinline__ void put_nu(const AHalo<S>& h, float* sa, float* snu)
   const float third = 1.0f / 3.0f, twelfth = 1.0f / 12.0f;
   const float* sx = sa;
   const float* sy = sa + L::NA;
-  for (int p = tid; p < S::LDS; p += S::NTHREADS) {
-    const int hx = p % S::LW, hy = p / S::LW;
+  HaloWalk<S::LW, S::NTHREADS> w(tid);
+  for (int p = tid; p < S::LDS; p += S::NTHREADS, w.next()) {
+    const int hx = w.hx, hy = w.hy;
     const int c = (hy + 1) * L::AW + hx + 1;  // the same node in the A halo
     // axis neighbours z - e_j: E -> c-1, W -> c+1, N -> c-AW, S -> c+AW
     const float axis = (sx[c - 1] - sx[c + 1]) + (sy[c - L::AW] - sy[c + L::AW]);
@@ -872,6 +892,11 @@ __device__ __forceinline__ void adjoint_tile(const float* __restrict__ fsrc, con
     stage_tile<S, StoreF32>(R, RefPoly<float>{}, f, rho, srho, nullptr);
   }
   put_nu<S>(h, sa, snu);  // its barriers cover srho too
+  struct {
+    char* p[11];
+  } Q;
+#pragma unroll
+  for (int i = 0; i < 11; ++i) Q.p[i] = reinterpret_cast<char*>(adj_out) + (size_t)i * N * 4;
 #pragma unroll
   for (int k = 0; k < S::NPT; ++k) {
     const int ly = threadIdx.y + k * S::WY, y = y0 + ly;
@@ -886,12 +911,11 @@ __device__ __forceinline__ void adjoint_tile(const float* __restrict__ fsrc, con
     float lf[9], agx = 0.0f, agy = 0.0f;
     collide_node_vjp<float>(f[k], gx, gy, c, lb[k], lf, agx, agy, th);
     const unsigned o = o0 + (unsigned)(k * S::WY) * rb;
-    char* out = reinterpret_cast<char*>(adj_out);
+    // uniform field bases and one 32-bit lane offset for the eleven stores
 #pragma unroll
-    for (int i = 0; i < 9; ++i)
-      __builtin_nontemporal_store(lf[i], reinterpret_cast<float*>(out + (size_t)i * N * 4 + o));
-    __builtin_nontemporal_store(agx, reinterpret_cast<float*>(out + 9 * N * 4 + o));
-    __builtin_nontemporal_store(agy, reinterpret_cast<float*>(out + 10 * N * 4 + o));
+    for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(lf[i], reinterpret_cast<float*>(Q.p[i] + o));
+    __builtin_nontemporal_store(agx, reinterpret_cast<float*>(Q.p[9] + o));
+    __builtin_nontemporal_store(agy, reinterpret_cast<float*>(Q.p[10] + o));
   }
 }
 
