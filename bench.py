@@ -452,6 +452,12 @@ def main():
     t_wall = time.perf_counter()
     derived, rho0, fp32 = step_leg(pkg, wl, timer, "fp32", n, args.steps, args.warmup, tr, width)
     t_wall = time.perf_counter() - t_wall
+    t_start = time.perf_counter()
+
+    def done(what):
+        print(f"bench.py: {what} done ({time.perf_counter() - t_start:.0f} s)", file=sys.stderr, flush=True)
+
+    done("fp32 step leg")
     legs = {}
     if not args.only_fp32:
         for st in ("fp16", "bf16"):
@@ -459,14 +465,21 @@ def main():
             leg["ratio_vs_fp32"] = round(leg["mlups"] / fp32["mlups"], 4)
             leg["coexistence"] = coexistence_leg(pkg, wl, st)
             legs[st] = leg
+            done(f"{st} step leg")
         legs["fp32_coexistence"] = coexistence_leg(pkg, wl, "fp32")
         legs["coalescence_16384x8192"] = coalescence_legs(pkg, wl, timer)
+        done("16384x8192 legs")
         legs["elliptic_droplet"] = ellipse_leg(pkg, wl)
+        done("elliptic droplet")
         legs["head_on_collision"] = head_on_leg(pkg, wl)
+        done("head-on collisions")
         legs["fwd_adjoint"] = fwd_adjoint_leg(pkg, wl, timer, torch)
         legs["fwd_adjoint_keep_all_states"] = fwd_adjoint_leg(pkg, wl, timer, torch, every=1)
+        done("forward + adjoint legs")
         legs["fwd_adjoint"]["adjoint_kernel"] = adjoint_kernel_leg(pkg, wl, timer, torch)
         legs["fwd_adjoint"]["gradient"] = gradient_error(pkg, wl, timer, torch)
+        done("adjoint kernel and gradient legs")
+    pacer.close()
 
     out = {
         "metric": METRIC,
