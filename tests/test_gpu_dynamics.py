@@ -63,24 +63,29 @@ def test_elliptic_droplet_period():
 
 def liquid_bodies(rho, level):
     """Connected regions with rho > level (4-connected; the droplets stay
-    clear of the lattice edges), as (size, x centroid) pairs, specks of up
-    to 20 nodes left out."""
+    clear of the lattice edges), as (size, x centroid, y centroid), specks
+    of up to 20 nodes left out."""
     lab, count = ndimage.label(rho > level)
     idx = range(1, count + 1)
     sizes = ndimage.sum(np.ones_like(rho), lab, idx)
-    cx = [c[1] for c in ndimage.center_of_mass(np.ones_like(rho), lab, idx)]
-    return [(s, x) for s, x in zip(sizes, cx) if s > 20]
+    cm = ndimage.center_of_mass(np.ones_like(rho), lab, idx)
+    return [(s, c[1], c[0]) for s, c in zip(sizes, cm) if s > 20]
 
 
 # We, Re and the dimensionless end time t* = t U / D of each run
-HEAD_ON = {"merge": (0.01, 1.0, 2.5), "bounce": (0.1, 1.0, 6.0)}
+HEAD_ON = {"merge": (0.01, 1.0, 2.5), "bounce": (0.1, 1.0, 6.0), "merge_large_deformation": (20.0, 100.0, 12.0),
+           "satellite": (60.0, 200.0, 20.0)}
 
 
-@pytest.mark.parametrize("regime", ["merge", "bounce"])
-def test_head_on_collision_low_weber(regime):
+@pytest.mark.parametrize("regime", ["merge", "bounce", "merge_large_deformation", "satellite"])
+def test_head_on_collision_regimes(regime):
     """Head-on collision of equal droplets, D = 128 on 1024^2, T_r = 0.7,
     W = 10 (main text, dynamic problems): at We = 0.01, Re = 1 the droplets
-    merge; at We = 0.1, Re = 1 they bounce back without merging.
+    merge; at We = 0.1, Re = 1 they bounce back without merging; at We = 20,
+    Re = 100 they merge with large deformation; at We = 60, Re = 200 the
+    merged mass splits into two droplets with a satellite at the centre.
+    The last two run at s_p = 1.645 and 1.685, near the stability limit at
+    this density ratio (from gaps of 80 nodes they diverge).
     We = rho_l U^2 D / sigma and Re = U D / nu fix the relative speed U and
     the shear rate s_p (nu = (1/s_p - 1/2)/3), with sigma the sound-speed
     value.  The paper states neither the initial separation nor the velocity
@@ -115,10 +120,22 @@ def test_head_on_collision_low_weber(regime):
     assert abs(tot[0] / mass0 - 1.0) < 1e-3
     if regime == "merge":
         assert counts[0] == 2 and counts[-1] == 1
-    else:
+    elif regime == "bounce":
         assert all(c == 2 for c in counts)
         i = int(np.argmin(sep))
         assert 0 < i < nsamp - 1 and sep[-1] > sep[i] + 5.0  # closest approach, then apart
+    elif regime == "merge_large_deformation":
+        assert all(c == 1 for c in counts)  # merged by t* = 1 and stays one body
+    else:  # the merged mass splits into two droplets with a satellite between them
+        print("bodies at the end (size, x, y):", [tuple(round(float(v), 1) for v in b) for b in history[-1]])
+        assert counts[0] == 1 and counts[-1] == 3
+        # one body at the collision point, two equal ones placed symmetrically about it
+        by_dist = sorted(history[-1], key=lambda b: np.hypot(b[1] - n / 2, b[2] - n / 2))
+        sat, a, b = by_dist
+        assert np.hypot(sat[1] - n / 2, sat[2] - n / 2) < 0.02 * n
+        assert np.hypot(0.5 * (a[1] + b[1]) - n / 2, 0.5 * (a[2] + b[2]) - n / 2) < 0.02 * n
+        assert abs(a[0] - b[0]) <= 0.05 * max(a[0], b[0])
+        assert min(np.hypot(a[1] - n / 2, a[2] - n / 2), np.hypot(b[1] - n / 2, b[2] - n / 2)) > D
 
 
 def test_elliptic_droplet_window_at_peak_velocity():
