@@ -3,21 +3,31 @@
 
 Headline workload: spinodal decomposition on a periodic 4096 x 4096 lattice
 at T/T_c = 0.7 (mean of the coexistence densities plus seeded uniform noise
-+-0.01), W = 10, sigma from the paper's sound-speed rule.  A step is one
-fused launch (density halo, force, collision, streaming).  Inputs are
-resident in HBM before any timed region starts; every timed region is
-bracketed by HIP events on the stream the kernels are launched on.
++-0.01), W = 10, sigma from the paper's sound-speed rule.  lbm_step(n)
+advances FP32 states two steps per launch (density halo, force, collision
+and streaming of two time steps in one kernel, the same bits as two single
+steps); the 2-byte storages take one step per launch.  Inputs are resident
+in HBM before any timed region starts; every timed region is bracketed by
+HIP events on the stream the kernels are launched on.
 
 Prints one JSON line:
-  value / roofline   MLUPS of the FP32 step and its HBM roofline fraction
-                     (72 algorithmic bytes per lattice update);
-  legs.fp16, .bf16   the same step with 2-byte storage of f (40 B/LU), the
-                     ratio to FP32, and the coexistence-density error of a
-                     relaxed flat interface against the Maxwell densities;
-                     these steps are bound by the vector ALU, and every step
-                     leg also carries `alu`, its vector-ALU roofline (lane-
-                     instructions per update from the committed rocprofv3 SQ
-                     summary times the update rate, against 39.3e12/s);
+  value / roofline   MLUPS of the FP32 path (lbm_step) and the roofline of
+                     its two-step kernel, which is bound by the vector ALU:
+                     230 algorithmic lane-instructions per update (one
+                     update's arithmetic in the gfx950 assembly) times the
+                     update rate against the non-packed vector peak
+                     39.3e12/s; its HBM view beside it (36 algorithmic bytes
+                     per update: f read and written once per two updates);
+  legs.fp32_single_step  one lbm_step(1) call per step: the one-step kernel,
+                     bound by HBM (72 B/LU), with its HBM roofline;
+  legs.fp16, .bf16   the step with 2-byte storage of f (40 B/LU, one step per
+                     launch), its ratio to both FP32 paths, and the
+                     coexistence-density error of a relaxed flat interface
+                     against the Maxwell densities; these steps are bound by
+                     the vector ALU, and every step leg also carries `alu`,
+                     its vector-ALU roofline (lane-instructions per update
+                     from the committed rocprofv3 SQ summary times the update
+                     rate, against 39.3e12/s);
   legs.fwd_adjoint   checkpointed forward + adjoint over 1000 steps of the
                      2048^2 droplet-pair crop (T/T_c = 0.6, K = 100), the
                      adjoint kernel's own roofline, and the gradient error of
@@ -48,23 +58,47 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "MLUPS + % HBM roofline, FP32 vs FP16-storage step; fwd+adjoint MLUPS at stated err"
 HBM_PEAK_GBS = 8000.0
 # Algorithmic HBM bytes per lattice update (LU):
-#   step: 9 populations read + 9 written (4 B, or 2 B plus the 2-byte reference density read and written);
+#   one-step kernel: 9 populations read + 9 written (4 B, or 2 B plus the 2-byte reference density read and written);
+#   two-step kernel (FP32): 9 populations read + 9 written per node and launch, two updates;
 #   adjoint step: f(t) 9 + L 9 + force adjoint 2 read, L 9 + force adjoint 2 written (4 B each).
 BYTES_PER_LU = {"fp32": 72, "fp16": 40, "bf16": 40}
+STEP2_BYTES_PER_LU = 36
+# Vector instructions of one update's arithmetic (density 8, stencil 13.5,
+# forward transform 25.5, node state and EOS 28, six-step collision 123,
+# f += M^T w 31.5: the gfx950 assembly of the one-step kernel, per node),
+# the algorithmic work against which the two-step kernel's ALU roofline is
+# priced (its halo recomputation and addressing are overhead, like re-read
+# bytes in an HBM-bound kernel).
+ALG_INSTR_PER_LU = 230
 ADJ_BYTES_PER_LU = 124
 # the same without the two force-adjoint planes: f(t) 9 + lambda 9 read, lambda 9 written
 ADJ_MIN_BYTES_PER_LU = 108
 # rocprofv3 FETCH_SIZE / WRITE_SIZE summaries of each kernel on the 4096^2 workload
 PROFILE_TRAFFIC = {k: os.path.join(ROOT, "profiles", f"traffic_{k}_spinodal4096.json")
-                   for k in ("step_f32", "step_f16", "step_bf16", "adjoint_f32")}
+                   for k in ("step2_f32", "step_f32", "step_f16", "step_bf16", "adjoint_f32")}
 # rocprofv3 SQ summaries: vector instructions per lattice update of each kernel
 PROFILE_VALU = {k: os.path.join(ROOT, "profiles", f"valu_{k}_spinodal4096.json")
-                for k in ("step_f32", "step_f16", "step_bf16", "adjoint_f32")}
+                for k in ("step2_f32", "step_f32", "step_f16", "step_bf16", "adjoint_f32")}
 # Vector-ALU peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # = 39.3e12 lane-instructions per second (one FP32 FMA each: 78.6 TFLOP/s,
 # half the 157.3 TFLOP/s of packed FP32, which the library is compiled without).
 VALU_PEAK_TLANE = 256 * 4 * 16 * 2.4e9 / 1e12
 GOLDEN = os.path.join(ROOT, "tests", "golden", "droplet512_gradients.json")
+
+
+def headline_roofline(fp32):
+    """Roofline of the two-step FP32 kernel: bound by the vector ALU, priced
+    on ALG_INSTR_PER_LU per update; traffic is its measured HBM bytes per
+    launch (two updates per node); its HBM view on 36 B per update beside."""
+    achieved = ALG_INSTR_PER_LU * fp32["mlups"] * 1e6 / 1e12
+    alu = fp32["alu"] or {}
+    return {"bound": "alu", "achieved": round(achieved, 2), "peak": round(VALU_PEAK_TLANE, 2),
+            "unit": "T lane-instr/s", "frac": round(achieved / VALU_PEAK_TLANE, 4), "traffic": fp32["traffic"],
+            "kernel": fp32["kernel"], "algorithmic_instr_per_lu": ALG_INSTR_PER_LU,
+            "executed_instr_per_lu_profiled": alu.get("valu_lane_instr_per_lu"),
+            "valu_busy_profiled": alu.get("valu_busy_profiled"),
+            "hbm": {"achieved": fp32["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fp32["frac"],
+                    "algorithmic_bytes_per_lu": STEP2_BYTES_PER_LU}}
 
 
 def kernel_source_hash():
@@ -147,23 +181,39 @@ def make_pacer(pkg, wl, n=4096, tr=0.7, width=10.0):
         wl.spinodal({"rho_g": d.rho_g, "rho_l": d.rho_l, "width": width}, n=n, seed=4))
 
 
-def step_leg(pkg, wl, timer, storage, n, steps, warmup, tr=0.7, width=10.0):
+def step_leg(pkg, wl, timer, storage, n, steps, warmup, tr=0.7, width=10.0, single=False):
+    """`steps` steps of the 4096^2 spinodal workload in one lbm_step call
+    (FP32: the two-step kernel), or with single=True one lbm_step(1) call
+    per step (the one-step kernel)."""
     d = pkg.lbm_derive(pkg.make_params(n, n, tr=tr, width=width))
     rho0 = wl.spinodal({"rho_g": d.rho_g, "rho_l": d.rho_l, "width": width}, n=n)
     lat = pkg.Lattice(n, n, tr=tr, width=width, storage=storage).init(rho0)
-    ms = timer(lambda: lat.step(steps), pre=lambda: lat.step(warmup))
+
+    def run(k):
+        if single:
+            for _ in range(k):
+                lat.step(1)
+        else:
+            lat.step(k)
+
+    ms = timer(lambda: run(steps), pre=lambda: run(warmup))
     tot = lat.moments(fields=False)
     lat.close()
     if not all(np.isfinite(tot)):
         raise RuntimeError(f"{storage} state diverged")
     per = ms / steps
-    gbs = BYTES_PER_LU[storage] * n * n / (per * 1e-3) / 1e9
+    two_step = storage == "fp32" and not single
+    alg = STEP2_BYTES_PER_LU if two_step else BYTES_PER_LU[storage]
+    gbs = alg * n * n / (per * 1e-3) / 1e9
     mlups = round(n * n * steps / (ms * 1e-3) / 1e6, 1)
-    kernel = "step_" + storage.replace("fp", "f")
+    kernel = "step2_f32" if two_step else "step_" + storage.replace("fp", "f")
+    traffic = measured_traffic(kernel, n * n)
     return d, rho0, {"mlups": mlups, "ms_per_step": round(per, 5),
+                     "kernel": ("step2_kernel<F32>, two steps per launch" if two_step
+                                else f"step_kernel<{storage.upper()}>, one step per launch"),
                      "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
-                     "algorithmic_bytes_per_lu": BYTES_PER_LU[storage],
-                     "traffic": measured_traffic(kernel, n * n), "alu": alu_roofline(kernel, n * n, mlups)}
+                     "algorithmic_bytes_per_lu": alg,
+                     "traffic": traffic, "alu": alu_roofline(kernel, n * n, mlups)}
 
 
 def _semi_axis(profile, level):
@@ -175,12 +225,29 @@ def _semi_axis(profile, level):
     return 0.5 * (hi - lo)
 
 
+def field_split(rho, ref, d):
+    """Difference of a density field from ref split by the phase of ref: the
+    largest density difference over bulk nodes (ref outside the middle 80 %
+    of [rho_g, rho_l]), in rho_l, and over interface nodes the largest
+    displacement |rho - ref| / |grad ref| in lattice spacings."""
+    import torch
+    span = d.rho_l - d.rho_g
+    iface = (ref > d.rho_g + 0.1 * span) & (ref < d.rho_l - 0.1 * span)
+    diff = (rho - ref).abs()
+    gx = 0.5 * (torch.roll(ref, -1, 1) - torch.roll(ref, 1, 1))
+    gy = 0.5 * (torch.roll(ref, -1, 0) - torch.roll(ref, 1, 0))
+    g = torch.sqrt(gx * gx + gy * gy)
+    return diff[~iface].max().item() / d.rho_l, (diff[iface] / g[iface]).max().item()
+
+
 def coalescence_legs(pkg, wl, timer, nx=16384, ny=8192, steps=5000, warmup=20):
     """The largest workload: two R = 400 droplets 20 nodes apart on
     16384 x 8192 at T/T_c = 0.6 (9.7 GB of FP32 A/B buffers), its 5000 steps
-    timed per storage, then the read-outs at t = 5000 of each 2-byte run
-    against the FP32 run: field max |d rho| / rho_l, gap density, liquid
-    bodies, the droplets' vertical semi-axes, liquid and gas densities."""
+    timed per storage (FP32: the two-step kernel, 36 B/LU), then the
+    read-outs at t = 5000 of each 2-byte run against the FP32 run: field
+    max |d rho| / rho_l, split into bulk density and interface displacement,
+    gap density, liquid bodies, the droplets' vertical semi-axes, liquid and
+    gas densities."""
     from scipy import ndimage
     import torch
     d = pkg.lbm_derive(pkg.make_params(nx, ny, tr=0.6, width=10.0))
@@ -194,7 +261,7 @@ def coalescence_legs(pkg, wl, timer, nx=16384, ny=8192, steps=5000, warmup=20):
         rho = lat.moments()[0]
         lat.close()
         per = ms / steps
-        gbs = BYTES_PER_LU[storage] * nx * ny / (per * 1e-3) / 1e9
+        gbs = (STEP2_BYTES_PER_LU if storage == "fp32" else BYTES_PER_LU[storage]) * nx * ny / (per * 1e-3) / 1e9
         region = rho[cy - 600:cy + 600, cx - 1100:cx + 1100].double().cpu().numpy()
         lab, count = ndimage.label(region > level)
         sizes = ndimage.sum(np.ones_like(region), lab, range(1, count + 1))
@@ -209,6 +276,9 @@ def coalescence_legs(pkg, wl, timer, nx=16384, ny=8192, steps=5000, warmup=20):
             ref = rho
         else:
             leg["t5000"]["max_drho_vs_fp32_rel_rho_l"] = float((rho - ref).abs().max().item() / d.rho_l)
+            bulk, disp = field_split(rho, ref, d)
+            leg["t5000"]["bulk_max_drho_vs_fp32_rel_rho_l"] = bulk
+            leg["t5000"]["interface_max_displacement_vs_fp32"] = disp
             del rho
         out[storage] = leg
         torch.cuda.empty_cache()
@@ -459,10 +529,14 @@ def main():
 
     done("fp32 step leg")
     legs = {}
+    _, _, single = step_leg(pkg, wl, timer, "fp32", n, args.steps, args.warmup, tr, width, single=True)
+    legs["fp32_single_step"] = single
+    done("fp32 single-step leg")
     if not args.only_fp32:
         for st in ("fp16", "bf16"):
             _, _, leg = step_leg(pkg, wl, timer, st, n, args.steps, args.warmup, tr, width)
             leg["ratio_vs_fp32"] = round(leg["mlups"] / fp32["mlups"], 4)
+            leg["ratio_vs_fp32_single_step"] = round(leg["mlups"] / single["mlups"], 4)
             leg["coexistence"] = coexistence_leg(pkg, wl, st)
             legs[st] = leg
             done(f"{st} step leg")
@@ -496,9 +570,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"spinodal decomposition {n}x{n}, T/Tc={tr}, W={width}, "
                                f"sigma={derived.sigma:.6g}", "nx": n, "ny": n, "storage": "fp32"},
-        "roofline": {"bound": "hbm", "achieved": fp32["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": fp32["frac"], "traffic": fp32["traffic"], "kernel": "step_kernel<F32>",
-                     "algorithmic_bytes_per_lu": BYTES_PER_LU["fp32"]},
+        "roofline": headline_roofline(fp32),
         "legs": legs,
         "wall_s_fp32_leg": round(t_wall, 3),
         "lead_in": {"steps": timer.lead_in_steps, "lattice": "4096x4096 FP32, its own spinodal state",

@@ -60,6 +60,18 @@ __host__ __device__ __forceinline__ T recip(T x) {
   return T(1) / x;
 }
 
+// a b + c with one rounding.  The functions of the forward step below
+// disable contraction (fp contract off) and fuse where they say so, so
+// that a node's update is the same sequence of roundings in every kernel
+// that inlines them, whatever products the compiler would otherwise fuse.
+template <typename T>
+__host__ __device__ __forceinline__ T fma_(T a, T b, T c) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_fmaf(a, b, c);
+  else
+    return __builtin_fma(a, b, c);
+}
+
 // rho = sum_i f_i in one fixed order (the order forward_moments uses), so a
 // node's density is the same number in every kernel that forms it.
 template <typename T>
@@ -73,10 +85,11 @@ __host__ __device__ __forceinline__ T density(const T* f) {
 template <typename T>
 __host__ __device__ __forceinline__ void stencil(T rE, T rN, T rW, T rS, T rNE, T rNW, T rSW, T rSE, T& gx,
                                                  T& gy) {
+#pragma clang fp contract(off)
   const T third = T(1) / T(3), twelfth = T(1) / T(12);
   const T dd1 = rNE - rSW, dd2 = rSE - rNW;  // the two diagonals
-  gx = third * (rE - rW) + twelfth * (dd1 + dd2);
-  gy = third * (rN - rS) + twelfth * (dd1 - dd2);
+  gx = fma_(twelfth, dd1 + dd2, third * (rE - rW));
+  gy = fma_(twelfth, dd1 - dd2, third * (rN - rS));
 }
 
 // Pressure of the lattice Boltzmann equation and its density slope:
@@ -84,13 +97,14 @@ __host__ __device__ __forceinline__ void stencil(T rE, T rN, T rW, T rS, T rNE, 
 // Z = (1 + v + v^2 - v^3)/(1 - v)^3, d(rho Z)/d rho = (1 + 4v + 4v^2 - 4v^3 + v^4)/(1 - v)^4.
 template <typename T>
 __host__ __device__ __forceinline__ void eos(T rho, const Coef<T>& c, T& p_lbe, T& dp_lbe) {
+#pragma clang fp contract(off)
   const T v = c.b4 * rho;
   const T iw = recip(T(1) - v);
   const T iw3 = iw * iw * iw;
-  const T z = (T(1) + v * (T(1) + v * (T(1) - v))) * iw3;
-  const T dz = (T(1) + v * (T(4) + v * (T(4) + v * (v - T(4))))) * (iw3 * iw);
-  p_lbe = rho * (c.kprt * z + c.e_rho * rho);
-  dp_lbe = c.kprt * dz + c.de_rho * rho;
+  const T z = fma_(v, fma_(v, T(1) - v, T(1)), T(1)) * iw3;
+  const T dz = fma_(v, fma_(v, fma_(v, v - T(4), T(4)), T(4)), T(1)) * (iw3 * iw);
+  p_lbe = rho * fma_(c.kprt, z, c.e_rho * rho);
+  dp_lbe = fma_(c.kprt, dz, c.de_rho * rho);
 }
 
 // m = M f (supplement Eq. 4) as an add/subtract tree; m[0] is density(f).
@@ -141,15 +155,16 @@ struct NodeState {
 
 template <typename T>
 __host__ __device__ __forceinline__ NodeState<T> node_state(T rho, T jx, T jy, T gx, T gy, const Coef<T>& c) {
+#pragma clang fp contract(off)
   NodeState<T> s;
   s.rho = rho;
   s.Fx = c.g2 * rho * gx;
   s.Fy = c.g2 * rho * gy;
   const T inv = recip(rho);
-  s.ux = (jx + T(0.5) * s.Fx) * inv;
-  s.uy = (jy + T(0.5) * s.Fy) * inv;
+  s.ux = fma_(T(0.5), s.Fx, jx) * inv;
+  s.uy = fma_(T(0.5), s.Fy, jy) * inv;
   eos(rho, c, s.p_lbe, s.dp_lbe);
-  s.eta = T(3) * s.p_lbe - rho;  // p_LBE = (rho + eta)/3 (main Eq. 9, alpha1 = -1, beta1 = 1)
+  s.eta = fma_(T(3), s.p_lbe, -rho);  // p_LBE = (rho + eta)/3 (main Eq. 9, alpha1 = -1, beta1 = 1)
   return s;
 }
 
@@ -167,41 +182,55 @@ __host__ __device__ __forceinline__ NodeState<T> node_state(T rho, T jx, T jy, T
 template <typename T>
 __host__ __device__ __forceinline__ void collide_scaled(const T* m, const NodeState<T>& s, T gx, T gy,
                                                         const Coef<T>& c, T* w) {
+#pragma clang fp contract(off)
   const T rho = s.rho, ux = s.ux, uy = s.uy, Fx = s.Fx, Fy = s.Fy, dp = s.dp_lbe;
   const T ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy, u2 = ux2 + uy2, dxy = ux2 - uy2;
   const T c3x = ux * ux2, c3y = uy * uy2, cxyy = uxy * uy, cxxy = uxy * ux;
-  // equilibrium moments (main Eq. 3) and half force moments (main Eq. 4)
-  const T meq1 = T(2) * (s.eta - rho) + T(3) * rho * u2;
-  const T meq2 = c.alpha2 * rho + c.beta2 * s.eta + rho * (T(9) * ux2 * uy2 - T(3) * u2);
-  const T meq4 = rho * (T(3) * cxyy - ux), meq6 = rho * (T(3) * cxxy - uy);
-  const T meq7 = rho * dxy, meq8 = rho * uxy;
+  // half force moments (main Eq. 4; hF8 = 2 F_m8 / 2)
   const T Fxu = Fx * ux, Fyu = Fy * uy;
   const T Fu3 = T(3) * (Fxu + Fyu);
-  const T hF2 = T(9) * (Fx * cxyy + Fy * cxxy) - Fu3;
-  const T hF4 = T(1.5) * (Fx * uy2 + T(2) * Fy * uxy) - T(0.5) * Fx;
-  const T hF6 = T(1.5) * (Fy * ux2 + T(2) * Fx * uxy) - T(0.5) * Fy;
+  const T hF2 = fma_(T(9), fma_(Fx, cxyy, Fy * cxxy), -Fu3);
+  const T hF4 = fma_(Fx, fma_(T(1.5), uy2, T(-0.5)), T(3) * Fy * uxy);
+  const T hF6 = fma_(Fy, fma_(T(1.5), ux2, T(-0.5)), T(3) * Fx * uxy);
   const T hF7 = Fxu - Fyu;
-  const T hF8 = T(0.5) * (Fx * uy + Fy * ux);
-  // (1) d = m - m^eq + F_m/2
-  const T d1 = m[1] - meq1 + Fu3, d2 = m[2] - meq2 + hF2, d4 = m[4] - meq4 + hF4;
-  const T d6 = m[6] - meq6 + hF6, d7 = m[7] - meq7 + hF7, d8 = m[8] - meq8 + hF8;
+  const T hF8 = fma_(Fx, uy, Fy * ux);
+  // (1) d = m - m^eq + F_m/2 with the equilibrium moments of main Eq. 3
+  const T meq2 = fma_(rho, fma_(T(9) * ux2, uy2, T(-3) * u2), fma_(c.alpha2, rho, c.beta2 * s.eta));
+  const T d1 = fma_(T(-3) * rho, u2, fma_(T(-2), s.eta - rho, m[1])) + Fu3;
+  const T d2 = m[2] - meq2 + hF2;
+  const T d4 = fma_(-rho, fma_(T(3), cxyy, -ux), m[4]) + hF4;
+  const T d6 = fma_(-rho, fma_(T(3), cxxy, -uy), m[6]) + hF6;
+  const T d7 = fma_(-rho, dxy, m[7]) + hF7;
+  const T d8 = fma_(T(0.5), hF8, fma_(-rho, uxy, m[8]));
   // (2)-(3) D = (1 - s/2)(d + N d)
-  const T D1 = c.om_e * (d1 + c.k_seps_h * d2 + c.h_sq_h * (ux * d4 + uy * d6));
-  const T D7 = c.om_p * (d7 + c.b_sq * (ux * d4 - uy * d6));
-  const T D8 = c.om_p * (d8 + c.b_sq_h * (uy * d4 + ux * d6));
+  const T D1 = c.om_e * fma_(c.h_sq_h, fma_(ux, d4, uy * d6), fma_(c.k_seps_h, d2, d1));
+  const T D7 = c.om_p * fma_(c.b_sq, fma_(ux, d4, -(uy * d6)), d7);
+  const T D8 = c.om_p * fma_(c.b_sq_h, fma_(uy, d4, ux * d6), d8);
   // (4) corrections with (5) m-bar - m = 2 (D - d + F_m/2) - corrections and
   // (6) S Q_m, each row times its factor of D
-  const T gg = gx * gx + gy * gy;
-  const T b1 = dp * c.w_x1 + c.w_t1b, b7 = dp * c.w_x7 + c.w_t7b, b8 = dp * c.w_x8 + c.w_t8;
-  w[1] = T(2.0 / 36.0) * ((D1 - d1) + Fu3) + c.w_r11 * u2 * D1 + c.w_r17 * dxy * D7 + c.w_r18 * uxy * D8 +
-         (c.w_t1a * c3x + b1 * cxyy) * gx + (c.w_t1a * c3y + b1 * cxxy) * gy + c.w_q1 * gg;
-  w[2] = T(2.0 / 36.0) * hF2 - c.w_seps * d2 - c.w_q2 * gg;
-  w[4] = T(1.0 / 6.0) * hF4 - c.w_sq * d4;
-  w[6] = T(1.0 / 6.0) * hF6 - c.w_sq * d6;
-  w[7] = T(0.5) * ((D7 - d7) + hF7) + c.w_r71 * dxy * D1 + c.w_r77 * u2 * D7 +
-         (c.w_t7 * c3x + b7 * cxyy) * gx - (c.w_t7 * c3y + b7 * cxxy) * gy + c.w_q7 * (gx * gx - gy * gy);
-  w[8] = T(0.5) * ((D8 - d8) + hF8) + c.w_r81 * uxy * D1 + c.w_r88 * u2 * D8 +
-         b8 * ((c3y + T(2) * cxxy) * gx + (c3x + T(2) * cxyy) * gy) + c.w_q7 * (gx * gy);
+  const T gg = fma_(gx, gx, gy * gy);
+  const T b1 = fma_(dp, c.w_x1, c.w_t1b), b7 = fma_(dp, c.w_x7, c.w_t7b), b8 = fma_(dp, c.w_x8, c.w_t8);
+  T a = T(2.0 / 36.0) * ((D1 - d1) + Fu3);
+  a = fma_(c.w_r11 * u2, D1, a);
+  a = fma_(c.w_r17 * dxy, D7, a);
+  a = fma_(c.w_r18 * uxy, D8, a);
+  a = fma_(fma_(c.w_t1a, c3x, b1 * cxyy), gx, a);
+  a = fma_(fma_(c.w_t1a, c3y, b1 * cxxy), gy, a);
+  w[1] = fma_(c.w_q1, gg, a);
+  w[2] = fma_(-c.w_q2, gg, fma_(-c.w_seps, d2, T(2.0 / 36.0) * hF2));
+  w[4] = fma_(-c.w_sq, d4, T(1.0 / 6.0) * hF4);
+  w[6] = fma_(-c.w_sq, d6, T(1.0 / 6.0) * hF6);
+  a = T(0.5) * ((D7 - d7) + hF7);
+  a = fma_(c.w_r71 * dxy, D1, a);
+  a = fma_(c.w_r77 * u2, D7, a);
+  a = fma_(fma_(c.w_t7, c3x, b7 * cxyy), gx, a);
+  a = fma_(-fma_(c.w_t7, c3y, b7 * cxxy), gy, a);
+  w[7] = fma_(c.w_q7, fma_(gx, gx, -(gy * gy)), a);
+  a = T(0.5) * fma_(T(0.5), hF8, D8 - d8);
+  a = fma_(c.w_r81 * uxy, D1, a);
+  a = fma_(c.w_r88 * u2, D8, a);
+  a = fma_(b8, fma_(fma_(T(2), cxxy, c3y), gx, fma_(T(2), cxyy, c3x) * gy), a);
+  w[8] = fma_(c.w_q7, gx * gy, a);
   w[3] = Fx * T(1.0 / 6.0);
   w[5] = Fy * T(1.0 / 6.0);
 }

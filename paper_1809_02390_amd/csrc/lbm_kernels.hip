@@ -544,6 +544,196 @@ __global__ __launch_bounds__(S::NTHREADS) void step_kernel(const void* __restric
   }
 }
 
+// ---------------------------------------------------------------------------
+// Two time steps per launch (FP32 storage).  A workgroup advances a TX x TY
+// tile from the state of time t to that of t + 2 without storing t + 1:
+//   (A) pull f(t) onto the tile plus a three-node ring and stage the
+//       densities of that region in LDS;
+//   (B) collide the tile plus a two-node ring (step t), streaming each
+//       post-collision population in LDS to the node it arrives at, if that
+//       node lies on the tile or its one-node ring;
+//   (C) form the densities of the tile and its ring at t + 1;
+//   (D) collide the tile (step t + 1) and store f-bar.
+// Every node is updated by the operations of step_kernel in the same order
+// (density, stencil, collide_node), so two fused steps give the bits of two
+// single steps.  Per two lattice updates the tile moves 36 B of each node in
+// and 36 B out, half the bytes of two single steps, for (TX+4)(TY+4) / (TX TY)
+// more collisions in step t: with 64 x 16 tiles the kernel is bound by the
+// vector ALU rather than by HBM.  kMid also stores the state of t + 1 (the
+// checkpoint driver keeps every state).
+// ---------------------------------------------------------------------------
+template <int TX_, int TY_, int WY_>
+struct Tile2Shape {
+  static constexpr int TX = TX_, TY = TY_, WY = WY_, NTHREADS = TX * WY;
+  static constexpr int W1 = TX + 6, H1 = TY + 6;  // loaded region: the tile and a three-node ring
+  static constexpr int KA = (H1 + WY - 1) / WY;   // loaded nodes of the tile's columns per thread
+  static constexpr int NSIDE = 6 * H1;            // loaded nodes left and right of the tile's columns
+  static constexpr int KD = TY / WY;              // tile nodes per thread
+  // the tile and its one-node ring (positions as in TileShape: LW, ring_slot)
+  static constexpr int LW = TX + 2, NRING = 2 * LW + 2 * TY, G = (TY + 2) * LW;
+  static_assert(TY % WY == 0, "rows per thread");
+  static_assert(NSIDE <= NTHREADS && NRING <= NTHREADS, "one side node and one ring node per thread");
+};
+#ifndef LBM_STEP2_TILE
+#define LBM_STEP2_TILE 64, 16, 4
+#endif
+using Step2Tile = Tile2Shape<LBM_STEP2_TILE>;
+
+// Whether the loaded region of the tile at (x0, y0) and its pull sources lie
+// inside the lattice without wrapping.
+template <class S>
+__device__ __forceinline__ bool interior_tile2(int x0, int y0, int nx, int ny) {
+  return x0 >= 4 && y0 >= 4 && x0 + S::TX + 4 <= nx && y0 + S::TY + 4 <= ny;
+}
+
+// Stencil gradient at position pos of an LDS density tile lw nodes wide.
+template <int LWD>
+__device__ __forceinline__ void stencil_at(const float* s, int pos, float& gx, float& gy) {
+  float nb[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) nb[i] = s[pos + kCy[i] * LWD + kCx[i]];
+  stencil(nb[1], nb[2], nb[3], nb[4], nb[5], nb[6], nb[7], nb[8], gx, gy);
+}
+
+// Stream the post-collision populations of the node at position (X, Y) of
+// the loaded region to the tile-plus-ring positions they arrive at: sg[i G +
+// (Y - 2 + e_iy) LW + X - 2 + e_ix], skipped where that lies outside.
+template <class S, bool kCheckX>
+__device__ __forceinline__ void push_node(const float* f, int X, int Y, float* sg) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int X2 = X - 2 + kCx[i], Y2 = Y - 2 + kCy[i];
+    const bool in = (unsigned)Y2 < (unsigned)(S::TY + 2) && (!kCheckX || (unsigned)X2 < (unsigned)S::LW);
+    if (in) sg[i * S::G + Y2 * S::LW + X2] = f[i];
+  }
+}
+
+template <class S, bool kMid>
+__global__ __launch_bounds__(S::NTHREADS) void step2_kernel(const float* __restrict__ src, float* __restrict__ mid,
+                                                            float* __restrict__ dst, int nx, int ny, int ntx,
+                                                            int ntiles, int strip, Coef<float> c) {
+  __shared__ float s1[S::W1 * S::H1];  // densities at t of the loaded region; then at t + 1 of tile + ring
+  __shared__ float sg[9 * S::G];       // populations arriving at the tile and its ring at t + 1
+  const size_t rowb = (size_t)36 * nx;  // bytes from one lattice row of a state to the next
+  const unsigned rb = 36u * (unsigned)nx, pb = 4u * (unsigned)nx;  // same; from one population to the next
+  int tx, ty;
+  strip_tile(xcd_tile(blockIdx.x, ntiles), ntx, ntiles / ntx, strip, tx, ty);
+  const int x0 = tx * S::TX, y0 = ty * S::TY;
+  const int lx = threadIdx.x, ly = threadIdx.y, tid = ly * S::TX + lx;
+  // side node of this thread: column sc of the six outside the tile's columns
+  const int sY = tid / 6, sc = tid - 6 * sY, sX = sc < 3 ? sc : S::TX + sc;
+  const bool side = tid < S::NSIDE;
+  float fa[S::KA][9], fs[9];
+  // (A) f(t) arriving at the loaded region, position (X, Y) = node (x0 - 3 + X, y0 - 3 + Y)
+  if (interior_tile2<S>(x0, y0, nx, ny)) {
+    // rows counted from y0 - 4; each population's pull shift in its uniform base
+    const char* sb = reinterpret_cast<const char*>(src) + (size_t)(y0 - 4) * rowb;
+    const char* Q[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Q[i] = sb + (ptrdiff_t)i * pb - (ptrdiff_t)kCy[i] * rb - kCx[i] * 4;
+    const unsigned o0 = (unsigned)(ly + 1) * rb + 4u * (unsigned)(x0 + lx);
+#pragma unroll
+    for (int k = 0; k < S::KA; ++k)
+      if (k * S::WY < S::H1 - (S::WY - 1) || ly + k * S::WY < S::H1) {
+        const unsigned o = o0 + (unsigned)(k * S::WY) * rb;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) fa[k][i] = ldb<float>(Q[i], o);
+      }
+    if (side) {
+      const unsigned o = (unsigned)(sY + 1) * rb + 4u * (unsigned)(x0 - 3 + sX);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) fs[i] = ldb<float>(Q[i], o);
+    }
+    asm volatile("; two-step loads issued: interior" ::: "memory");
+  } else {
+    const char* base = reinterpret_cast<const char*>(src);
+    const int xw = wrap(x0 + lx, nx);
+#pragma unroll
+    for (int k = 0; k < S::KA; ++k)
+      if (k * S::WY < S::H1 - (S::WY - 1) || ly + k * S::WY < S::H1)
+        pull_rows(base, xw, wrap(y0 - 3 + ly + k * S::WY, ny), nx, ny, fa[k]);
+    if (side) pull_rows(base, wrap(x0 - 3 + sX, nx), wrap(y0 - 3 + sY, ny), nx, ny, fs);
+    asm volatile("; two-step loads issued: edge" ::: "memory");
+  }
+  float ra[S::KA], rs = 0.f;
+#pragma unroll
+  for (int k = 0; k < S::KA; ++k) {
+    const int Y = ly + k * S::WY;
+    if (Y < S::H1) {
+      ra[k] = density(fa[k]);
+      s1[Y * S::W1 + lx + 3] = ra[k];
+    }
+  }
+  if (side) {
+    rs = density(fs);
+    s1[sY * S::W1 + sX] = rs;
+  }
+  __syncthreads();
+  // (B) step t on the tile and a two-node ring (Y in [1, H1 - 1), X in [1, W1 - 1))
+  char* const mb = kMid ? reinterpret_cast<char*>(mid) + (size_t)y0 * rowb : nullptr;
+#pragma unroll
+  for (int k = 0; k < S::KA; ++k) {
+    const int Y = ly + k * S::WY;
+    if (Y >= 1 && Y < S::H1 - 1) {
+      float gx, gy;
+      stencil_at<S::W1>(s1, Y * S::W1 + lx + 3, gx, gy);
+      collide_node<float>(fa[k], ra[k], gx, gy, c);
+      push_node<S, false>(fa[k], lx + 3, Y, sg);
+      if constexpr (kMid) {
+        const int r = Y - 3;  // tile row
+        if (r >= 0 && r < S::TY && x0 + lx < nx && y0 + r < ny) {
+          const unsigned o = (unsigned)r * rb + 4u * (unsigned)(x0 + lx);
+#pragma unroll
+          for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(fa[k][i], reinterpret_cast<float*>(mb + i * pb + o));
+        }
+      }
+    }
+  }
+  if (side && sc >= 1 && sc <= 4 && sY >= 1 && sY < S::H1 - 1) {
+    float gx, gy;
+    stencil_at<S::W1>(s1, sY * S::W1 + sX, gx, gy);
+    collide_node<float>(fs, rs, gx, gy, c);
+    push_node<S, true>(fs, sX, sY, sg);
+  }
+  __syncthreads();
+  // (C) densities at t + 1 of the tile (own nodes, kept in registers) and its ring
+  float fd[S::KD][9], rd[S::KD];
+  float* const s2 = s1;
+#pragma unroll
+  for (int k = 0; k < S::KD; ++k) {
+    const int pos = (ly + k * S::WY + 1) * S::LW + lx + 1;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fd[k][i] = sg[i * S::G + pos];
+    rd[k] = density(fd[k]);
+    s2[pos] = rd[k];  // the densities of step t are no longer read (barrier above)
+  }
+  if (tid < S::NRING) {
+    int hx, hy;
+    ring_slot<S>(tid, hx, hy);
+    const int pos = hy * S::LW + hx;
+    float fr[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fr[i] = sg[i * S::G + pos];
+    s2[pos] = density(fr);
+  }
+  __syncthreads();
+  // (D) step t + 1 on the tile
+  const int x = x0 + lx;
+  if (x >= nx) return;
+  char* const ob = reinterpret_cast<char*>(dst) + (size_t)y0 * rowb;
+#pragma unroll
+  for (int k = 0; k < S::KD; ++k) {
+    const int r = ly + k * S::WY;
+    if (y0 + r >= ny) break;
+    float gx, gy;
+    stencil_at<S::LW>(s2, (r + 1) * S::LW + lx + 1, gx, gy);
+    collide_node<float>(fd[k], rd[k], gx, gy, c);
+    const unsigned o = (unsigned)r * rb + 4u * (unsigned)x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(fd[k][i], reinterpret_cast<float*>(ob + i * pb + o));
+  }
+}
+
 // Deterministic FP64 sum of three per-thread values over a block, into this
 // block's slot partials[3 b .. 3 b + 2] (added to it if kAdd, else stored):
 // a fixed shuffle tree inside each wave, then the waves' sums in wave order.
@@ -1249,6 +1439,25 @@ void launch_step(const lbm_ctx* ctx, const void* src, void* dst, const uint16_t*
   launch_step_tiles<St, SmallTile>(ctx, src, dst, ref_in, ref_out);
 }
 
+// Two FP32 steps per launch (step2_kernel) on lattices with at least one
+// of its tiles per CU; smaller lattices take single steps on smaller tiles.
+#ifndef LBM_FUSE_STEPS
+#define LBM_FUSE_STEPS 1
+#endif
+bool use_step2(const lbm_ctx* ctx) {
+  return LBM_FUSE_STEPS && ctx->p.storage == LBM_FP32 && tiles_total<Step2Tile>(ctx->p.nx, ctx->p.ny) >= ctx->cus;
+}
+
+// src (time t) -> dst (time t + 2), and mid (time t + 1) if kMid.
+template <bool kMid>
+void launch_step2(const lbm_ctx* ctx, const void* src, void* mid, void* dst) {
+  using S = Step2Tile;
+  const int nx = ctx->p.nx, ny = ctx->p.ny, ntx = tiles_x<S>(nx), nt = tiles_total<S>(nx, ny);
+  step2_kernel<S, kMid><<<nt, dim3(S::TX, S::WY), 0, ctx->stream>>>(
+      static_cast<const float*>(src), static_cast<float*>(mid), static_cast<float*>(dst), nx, ny, ntx, nt,
+      strip_width(nx, S::TX, false), ctx->c);
+}
+
 int check_ctx(const lbm_ctx* ctx, bool need_state) {
   if (!ctx) return fail(LBM_EINVAL, "context is NULL");
   if (need_state && !ctx->ready) return fail(LBM_ESTATE, "state not initialised (call lbm_init or lbm_set_state)");
@@ -1434,9 +1643,15 @@ int lbm_step(lbm_ctx* ctx, int32_t n) {
   if (int st = set_device(ctx)) return st;
   int st = with_storage(ctx, [&](auto store) -> int {
     using St = decltype(store);
-    for (int32_t s = 0; s < n; ++s) {
+    for (int32_t s = 0; s < n;) {
       const int a = ctx->cur, b = ctx->cur ^ 1;
-      launch_step<St>(ctx, ctx->buf[a], ctx->buf[b], ctx->ref[a], ctx->ref[b]);
+      if (std::is_same_v<St, StoreF32> && n - s >= 2 && use_step2(ctx)) {
+        launch_step2<false>(ctx, ctx->buf[a], nullptr, ctx->buf[b]);
+        s += 2;
+      } else {
+        launch_step<St>(ctx, ctx->buf[a], ctx->buf[b], ctx->ref[a], ctx->ref[b]);
+        ++s;
+      }
       ctx->cur = b;
     }
     HIP_OK(hipGetLastError());
@@ -1567,7 +1782,16 @@ int lbm_step_saved_chain(lbm_ctx* ctx, void* const* bufs, int32_t n) {
     if (!bufs[j] || !bufs[j + 1] || bufs[j] == bufs[j + 1])
       return fail(LBM_EINVAL, "bufs[%d] and bufs[%d] must be two distinct device buffers", j, j + 1);
   if (int st = set_device(ctx)) return st;
-  for (int32_t j = 0; j < n; ++j) launch_step<StoreF32>(ctx, bufs[j], bufs[j + 1], nullptr, nullptr);
+  for (int32_t j = 0; j < n;) {
+    // two steps per launch where the state two steps on goes to a third buffer
+    if (n - j >= 2 && use_step2(ctx) && bufs[j + 2] != bufs[j]) {
+      launch_step2<true>(ctx, bufs[j], bufs[j + 1], bufs[j + 2]);
+      j += 2;
+    } else {
+      launch_step<StoreF32>(ctx, bufs[j], bufs[j + 1], nullptr, nullptr);
+      ++j;
+    }
+  }
   HIP_OK(hipGetLastError());
   return LBM_OK;
 }

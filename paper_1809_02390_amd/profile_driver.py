@@ -4,9 +4,12 @@ Runs, on the current GPU:
   1. a plain device-to-device copy of ``--copy-mib`` MiB, ``--copies`` times
      (the runtime's copy kernel: reads and writes exactly that many bytes),
      used to calibrate the FETCH_SIZE / WRITE_SIZE counters;
-  2. ``--steps`` launches of one library kernel on the 4096 x 4096 spinodal
+  2. ``--steps`` steps of one library kernel on the 4096 x 4096 spinodal
      workload (T/T_c = 0.7, W = 10):
-       --what step     the step kernel with the chosen --storage;
+       --what step     lbm_step(steps) with the chosen --storage (FP32: the
+                       two-step kernel, steps / 2 launches);
+       --what step1    FP32 single steps, one lbm_step(1) call each (the
+                       one-step kernel);
        --what adjoint  the FP32 adjoint step (forward state of the workload,
                        seeded adjoint, alternating adjoint buffers).
 
@@ -27,7 +30,7 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--storage", default="fp32")
-    ap.add_argument("--what", choices=("step", "adjoint"), default="step")
+    ap.add_argument("--what", choices=("step", "step1", "adjoint"), default="step")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--copies", type=int, default=3)
     args = ap.parse_args()
@@ -52,6 +55,9 @@ def main():
     lat = pkg.Lattice(n, n, tr=tr, width=width, storage=storage).init(rho0)
     if args.what == "step":
         lat.step(args.steps)
+    elif args.what == "step1":
+        for _ in range(args.steps):
+            lat.step(1)
     else:
         lat.step(5)
         ck = lat.save_state()

@@ -14,8 +14,8 @@ that a stale measurement is not reported.
 Instruction counters (one ``--pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU
 ... GRBM_GUI_ACTIVE`` run of ``profile_driver``): vector instructions per
 lattice update (SQ_INSTS_VALU counts wave instructions; times 64 lanes over
-the nodes of a launch) and the share of SIMD cycles with a vector
-instruction issued (SQ_ACTIVE_INST_VALU, in quad cycles, times 4 over
+the lattice updates of a launch, its nodes times --updates-per-node) and
+the share of SIMD cycles with a vector instruction issued (SQ_ACTIVE_INST_VALU, in quad cycles, times 4 over
 256 CUs x 4 SIMDs x GRBM_GUI_ACTIVE / 8, the GRBM count being summed over
 the eight XCDs).  Written to a JSON file that ``bench.py`` reads for the
 vector-ALU roofline of the kernels bound by it.
@@ -96,7 +96,8 @@ def counters(a):
         "fetch_kib_raw": fetch_k, "write_kib_raw": write_k, "dispatches": [nf, nw],
         "copy_fetch_kib_raw": copy_f, "copy_write_kib_raw": copy_w,
         "fetch_factor": ff, "write_factor": fw,
-        "bytes_per_launch": bytes_launch, "bytes_per_lu": bytes_launch / a.n_nodes,
+        "updates_per_node": a.updates_per_node,
+        "bytes_per_launch": bytes_launch, "bytes_per_lu": bytes_launch / (a.n_nodes * a.updates_per_node),
         "algorithmic_bytes_per_lu": a.algorithmic,
         "commands": a.command,
     }
@@ -120,7 +121,8 @@ def valu(a):
         "kernel": a.kernel + (f"<{a.storage_tag}>" if a.storage_tag else ""),
         "kernel_sha": kernel_source_hash(), "n_nodes": a.n_nodes, "dispatches": len(per),
         "waves": m["SQ_WAVES"], "valu_instr_per_wave": m["SQ_INSTS_VALU"] / m["SQ_WAVES"],
-        "valu_lane_instr_per_lu": m["SQ_INSTS_VALU"] * 64.0 / a.n_nodes,
+        "updates_per_node": a.updates_per_node,
+        "valu_lane_instr_per_lu": m["SQ_INSTS_VALU"] * 64.0 / (a.n_nodes * a.updates_per_node),
         "valu_busy": m["SQ_ACTIVE_INST_VALU"] * 4.0 / (256 * 4 * m["GRBM_GUI_ACTIVE"] / 8.0),
         "commands": a.command,
     }
@@ -175,6 +177,7 @@ def main():
     c.add_argument("--n-nodes", type=int, required=True)
     c.add_argument("--copy-mib", type=float, default=1024)
     c.add_argument("--algorithmic", type=float, default=None)
+    c.add_argument("--updates-per-node", type=int, default=1, help="lattice updates per node per launch")
     c.add_argument("--out", required=True)
     c.add_argument("--command", action="append", default=[], help="the rocprofv3 command lines (recorded)")
     v = sub.add_parser("valu")
@@ -182,6 +185,7 @@ def main():
     v.add_argument("--kernel", required=True)
     v.add_argument("--storage-tag", default=None)
     v.add_argument("--n-nodes", type=int, required=True)
+    v.add_argument("--updates-per-node", type=int, default=1, help="lattice updates per node per launch")
     v.add_argument("--out", required=True)
     v.add_argument("--command", action="append", default=[], help="the rocprofv3 command line (recorded)")
     t = sub.add_parser("trace")

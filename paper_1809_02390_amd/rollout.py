@@ -8,12 +8,13 @@ The map differentiated is
 with the parameters sigma, W and T_r entering through theta = (G'^2, K', R T)
 of the self-tuning EOS (main Eqs. 20-23).
 
-Forward: f(0) is saved once (lbm_save_state); the steps then run from
-checkpoint buffer to checkpoint buffer (lbm_step_saved_chain, the kernel of
-lbm_step), keeping the state of every ``every``-th step and passing the
-others through two scratch buffers.  Backward: from the last segment to the
-first, the segment's states are recomputed from its checkpoint (bit for bit
-the forward's) and the adjoint steps run back through them
+Forward: f(0) is saved once (lbm_save_state); the lattice then steps on
+(lbm_step, two steps per launch), its state copied to a checkpoint after
+every ``every``-th step; with every = 1 the steps run from checkpoint buffer
+to checkpoint buffer instead (lbm_step_saved_chain), so that no state is
+copied.  Backward: from the last segment to the first, the segment's states
+are recomputed from its checkpoint (lbm_step_saved_chain, bit for bit the
+forward's) and the adjoint steps run back through them
 (lbm_adjoint_run); lbm_adjoint_init closes with dL/d rho0, and
 
     dL/d(sigma, W, T_r) = J^T dL/d theta,   J = lbm_param_jacobian,
@@ -23,9 +24,10 @@ applied by the library (lbm_adjoint_params).
 Device memory: ceil(n / every) + 1 checkpoints + (every - 1) segment states
 + two adjoint states (11 fields each), all FP32 over nx*ny nodes.  With
 every = 1 every state is kept and nothing is recomputed (the forward +
-adjoint then moves 72 + 124 instead of 72 + 72 + 124 bytes per node and
-step; at 2048^2 x 1000 steps that is 151 GB of checkpoints, which HBM3E
-holds).  Any every > 1 recomputes n - ceil(n / every) forward steps, about
+adjoint then moves 54 + 124 instead of 36 + 54 + 124 bytes per node and
+step: the two-step kernel reads and writes each node's state once per two
+steps, 36 B per step, plus 18 B when it also stores the state between them;
+at 2048^2 x 1000 steps that is 151 GB of checkpoints, which HBM3E holds).  Any every > 1 recomputes n - ceil(n / every) forward steps, about
 the whole forward pass, so ``every="auto"`` keeps every state when they fit
 in free device memory and otherwise takes every = ceil(sqrt(n)), the
 interval that keeps the fewest states.  Every step of the path runs in the
@@ -44,7 +46,7 @@ def rollout_bytes(nsteps, every, state_bytes, adjoint_bytes):
     """Device bytes a Rollout holds besides the lattice's own buffers:
     checkpoints, segment states and the two adjoint states."""
     ckpt = -(-nsteps // every) + 1
-    pool = max(every - 1, 2) if every > 1 else 0
+    pool = every - 1
     return (ckpt + pool) * state_bytes + 2 * adjoint_bytes
 
 
@@ -83,7 +85,7 @@ class Rollout:
         self.nx, self.ny, self.nsteps, self.every = nx, ny, int(nsteps), int(every)
         self.starts = list(range(0, self.nsteps, self.every))
         self.ckpt = [None] * (len(self.starts) + 1)  # states at the starts, then the final state
-        self.pool = []  # segment states beyond the checkpoint (forward: the two scratch buffers)
+        self.pool = []  # segment states beyond the checkpoint (backward)
         self.inputs = None
 
     def _conv(self, a):
@@ -92,24 +94,22 @@ class Rollout:
         return torch.as_tensor(a).to(device=self.lat.f_a.device, dtype=torch.float32).reshape(
             self.ny, self.nx).contiguous()
 
-    def _buffer(self, k):
-        while len(self.pool) <= k:
-            self.pool.append(self.lat.checkpoint_buffer())
-        return self.pool[k]
-
     def forward(self, rho0, ux0=None, uy0=None):
         """rho_T (ny, nx) float32 after nsteps steps from f^eq(rho0)."""
         lat = self.lat
         self.inputs = (self._conv(rho0), self._conv(ux0), self._conv(uy0))
         lat.init(*self.inputs)
         self.ckpt[0] = lat.save_state(self.ckpt[0])
-        for s, t0 in enumerate(self.starts):
-            m = min(self.every, self.nsteps - t0)
-            if self.ckpt[s + 1] is None:
-                self.ckpt[s + 1] = lat.checkpoint_buffer()
-            chain = [self.ckpt[s]] + [self._buffer(j % 2) for j in range(m - 1)] + [self.ckpt[s + 1]]
-            lat.step_saved_chain(chain)
-        lat.load_state(self.ckpt[-1], self.nsteps)
+        if self.every == 1:
+            for s in range(len(self.starts)):
+                if self.ckpt[s + 1] is None:
+                    self.ckpt[s + 1] = lat.checkpoint_buffer()
+            lat.step_saved_chain(self.ckpt)
+            lat.load_state(self.ckpt[-1], self.nsteps)
+        else:
+            for s, t0 in enumerate(self.starts):
+                lat.step(min(self.every, self.nsteps - t0))
+                self.ckpt[s + 1] = lat.save_state(self.ckpt[s + 1])
         return lat.moments()[0]
 
     def _segment_states(self, s):

@@ -9,7 +9,7 @@ import torch
 import paper_1809_02390_amd as pkg
 import workloads as wl
 from oracle import lbm, measure
-from tests._gpu_helpers import (crop_periodic, device_samples, lattice, oracle_init, params_pair,
+from tests._gpu_helpers import (crop_periodic, device_samples, fp32_state_of, lattice, oracle_init, params_pair,
                                 sampled_oracle, sampled_oracle_moments)
 
 pytestmark = pytest.mark.gpu
@@ -142,6 +142,47 @@ def test_moments_fields_and_totals():
     mass, jx, jy = measure.totals(f)
     assert tot[0] == pytest.approx(mass, rel=1e-6)
     assert abs(tot[1] - jx) < 1e-6 * mass and abs(tot[2] - jy) < 1e-6 * mass
+
+
+@pytest.mark.parametrize("nx,ny,n", [(4096, 1024, 6), (1000, 700, 5), (2048 + 37, 1024 + 11, 7),
+                                     (16384, 8192, 2)])
+def test_two_step_launches_match_single_steps(nx, ny, n):
+    """lbm_step(n) on lattices with at least one 64 x 16 tile per CU runs
+    two steps per launch (interior tiles with 32-bit offsets, edge tiles
+    with wrapped 64-bit addresses, ragged tiles, an odd remainder as one
+    single step, and a state above 4 GiB): bitwise the result of n calls of
+    lbm_step(1)."""
+    _, co = params_pair(nx, ny, tr=0.7, width=10.0)
+    rng = np.random.default_rng(nx + ny)
+    rho = wl._f32(0.5 * (co.rho_g + co.rho_l) + rng.uniform(-0.01, 0.01, (ny, nx)))
+    a = lattice(nx, ny, rho, tr=0.7, width=10.0)
+    for _ in range(n):
+        a.step(1)
+    fa = a.state()
+    a.close()
+    b = lattice(nx, ny, rho, tr=0.7, width=10.0).step(n)
+    assert b.time == n and torch.equal(b.state(), fa)
+
+
+def test_two_step_chain_matches_single_steps():
+    """lbm_step_saved_chain over distinct buffers (two steps per launch,
+    the state between them written too) and over alternating buffers (one
+    step per launch): bitwise lbm_step_saved, step by step."""
+    nx, ny, n = 1000, 700, 5
+    _, co = params_pair(nx, ny, tr=0.7, width=10.0)
+    rho = wl.droplets(nx, ny, co.rho_g, co.rho_l, co.width, [(400, 300), (650, 420)], [120.0, 90.0])
+    lat = lattice(nx, ny, rho, tr=0.7, width=10.0)
+    single = [lat.save_state()] + [lat.checkpoint_buffer() for _ in range(n)]
+    for j in range(n):
+        lat.step_saved(single[j], single[j + 1])
+    distinct = [single[0]] + [lat.checkpoint_buffer() for _ in range(n)]
+    lat.step_saved_chain(distinct)
+    alternating = [single[0], lat.checkpoint_buffer(), lat.checkpoint_buffer()]
+    alternating = [alternating[0]] + [alternating[1 + j % 2] for j in range(n)]
+    lat.step_saved_chain(alternating)
+    state = lambda b: fp32_state_of(b, nx, ny)
+    assert all(torch.equal(state(x), state(y)) for x, y in zip(single, distinct))
+    assert torch.equal(state(alternating[-1]), state(single[-1]))
 
 
 def test_deterministic():

@@ -277,16 +277,35 @@ def coalescence_statistics(rho, co, nx, ny):
             "liquid": [float(rho[cy, x]) for x in centres], "gas": float(rho[0, 0])}
 
 
+def field_split(rho, ref, co):
+    """The difference of a density field rho from ref split by the phase of
+    ref: over bulk nodes (ref outside the middle 80 % of [rho_g, rho_l]) the
+    largest density difference, in rho_l; over interface nodes (inside) the
+    largest displacement |rho - ref| / |grad ref|, in lattice spacings (the
+    distance the interface would have moved to give that difference)."""
+    span = co.rho_l - co.rho_g
+    iface = (ref > co.rho_g + 0.1 * span) & (ref < co.rho_l - 0.1 * span)
+    d = (rho - ref).abs()
+    gx = 0.5 * (torch.roll(ref, -1, 1) - torch.roll(ref, 1, 1))
+    gy = 0.5 * (torch.roll(ref, -1, 0) - torch.roll(ref, 1, 0))
+    g = torch.sqrt(gx * gx + gy * gy)
+    bulk = d[~iface].max().item() / co.rho_l
+    disp = (d[iface] / g[iface]).max().item()
+    return bulk, disp
+
+
 def test_coalescence_5000_steps_against_fp32():
     """The 16384 x 8192 droplet pair (R = 400, gap 20, T_r = 0.6, density
     ratio 132) over its 5000 steps in FP32, FP16 and BF16.  Against the FP32
     run: the bulk liquid and gas densities within the coexistence bound
     (1e-3 rho_l), the gap density within it too, the same number of liquid
     bodies, each droplet's semi-axis within half a lattice spacing (the
-    storage may shift a curved interface but not by a node), and for FP16
-    the whole field within 1e-3 rho_l.  The BF16 field difference is
-    reported: it is the interface shift times the interface's density slope
-    (up to 0.06 rho per node), not a bulk error."""
+    storage may shift a curved interface but not by a node), and over the
+    whole field: at bulk nodes the density within 1e-3 rho_l, at interface
+    nodes the local displacement within half a lattice spacing.  The
+    whole-field maximum of |d rho| is reported: it sits on an interface,
+    where it is the displacement times the density slope (up to 0.1 rho_l
+    per node), so it mixes the two quantities the split gates separately."""
     nx, ny, steps = 16384, 8192, 5000
     _, co = params_pair(nx, ny, tr=0.6, width=10.0)
     rho0 = wl.coalescence(co, nx, ny)
@@ -301,14 +320,15 @@ def test_coalescence_5000_steps_against_fp32():
             ref = rho
             continue
         field = (rho - ref).abs().max().item() / co.rho_l
+        bulk, disp = field_split(rho, ref, co)
         s, r = stats[storage], stats["fp32"]
-        print(f"{storage}: max |d rho| / rho_l {field:.2e}, gap {s['gap']:.6f} (fp32 {r['gap']:.6f}), "
+        print(f"{storage}: max |d rho| / rho_l {field:.2e} (bulk {bulk:.2e}, interface displacement {disp:.3f}), "
+              f"gap {s['gap']:.6f} (fp32 {r['gap']:.6f}), "
               f"bodies {s['bodies']}, semi-axes {np.round(s['semi_axes'], 3)} (fp32 {np.round(r['semi_axes'], 3)})")
         assert s["bodies"] == r["bodies"] == 2
         assert abs(s["gap"] - r["gap"]) <= 1e-3 * co.rho_l
         assert abs(s["gas"] - r["gas"]) <= 1e-3 * co.rho_l
         assert max(abs(a - b) for a, b in zip(s["liquid"], r["liquid"])) <= 1e-3 * co.rho_l
         assert max(abs(a - b) for a, b in zip(s["semi_axes"], r["semi_axes"])) <= 0.5
-        if storage == "fp16":
-            assert field <= 1e-3, field
+        assert bulk <= 1e-3 and disp <= 0.5, (bulk, disp)
         del rho
