@@ -160,7 +160,7 @@ int lbm_get_state(lbm_ctx* ctx, float* f);
  * (the collision by the six steps of supplement Sec. IV), alternating A
  * and B.  Each step fuses the
  * density halo, the force, the collision and the streaming.  LBM_FP32 on
- * lattices with at least one 64 x 16 tile per compute unit: two steps per
+ * lattices with at least one 64 x 24 tile per compute unit: two steps per
  * kernel launch (the state between them is never written), then one for an
  * odd remainder; every node is updated by the same operations as in a
  * single step, so the result is bitwise that of n calls with n = 1.  The

@@ -557,10 +557,14 @@ __global__ __launch_bounds__(S::NTHREADS) void step_kernel(const void* __restric
 // Every node is updated by the operations of step_kernel in the same order
 // (density, stencil, collide_node), so two fused steps give the bits of two
 // single steps.  Per two lattice updates the tile moves 36 B of each node in
-// and 36 B out, half the bytes of two single steps, for (TX+4)(TY+4) / (TX TY)
-// more collisions in step t: with 64 x 16 tiles the kernel is bound by the
-// vector ALU rather than by HBM.  kMid also stores the state of t + 1 (the
-// checkpoint driver keeps every state).
+// and 36 B out, half the bytes of two single steps, for (TX+4)(TY+4)
+// collisions instead of TX TY in step t (64 x 24 tiles: 12 % more per
+// update over the two steps), so the kernel is bound by the vector ALU
+// rather than by HBM.  The tile is 64 x 24 in 512 threads (70 KB of LDS, two
+// workgroups per CU; measured at 4096^2 against 64 x 16 in 256 or 512
+// threads, 32 x 32, 64 x 20, 64 x 32, 128 x 16 and other thread counts).
+// kMid also stores the state of t + 1 (the checkpoint driver keeps every
+// state).
 // ---------------------------------------------------------------------------
 template <int TX_, int TY_, int WY_>
 struct Tile2Shape {
@@ -575,7 +579,7 @@ struct Tile2Shape {
   static_assert(NSIDE <= NTHREADS && NRING <= NTHREADS, "one side node and one ring node per thread");
 };
 #ifndef LBM_STEP2_TILE
-#define LBM_STEP2_TILE 64, 16, 4
+#define LBM_STEP2_TILE 64, 24, 8
 #endif
 using Step2Tile = Tile2Shape<LBM_STEP2_TILE>;
 
@@ -670,7 +674,6 @@ __global__ __launch_bounds__(S::NTHREADS) void step2_kernel(const float* __restr
   }
   __syncthreads();
   // (B) step t on the tile and a two-node ring (Y in [1, H1 - 1), X in [1, W1 - 1))
-  char* const mb = kMid ? reinterpret_cast<char*>(mid) + (size_t)y0 * rowb : nullptr;
 #pragma unroll
   for (int k = 0; k < S::KA; ++k) {
     const int Y = ly + k * S::WY;
@@ -679,14 +682,6 @@ __global__ __launch_bounds__(S::NTHREADS) void step2_kernel(const float* __restr
       stencil_at<S::W1>(s1, Y * S::W1 + lx + 3, gx, gy);
       collide_node<float>(fa[k], ra[k], gx, gy, c);
       push_node<S, false>(fa[k], lx + 3, Y, sg);
-      if constexpr (kMid) {
-        const int r = Y - 3;  // tile row
-        if (r >= 0 && r < S::TY && x0 + lx < nx && y0 + r < ny) {
-          const unsigned o = (unsigned)r * rb + 4u * (unsigned)(x0 + lx);
-#pragma unroll
-          for (int i = 0; i < 9; ++i) __builtin_nontemporal_store(fa[k][i], reinterpret_cast<float*>(mb + i * pb + o));
-        }
-      }
     }
   }
   if (side && sc >= 1 && sc <= 4 && sY >= 1 && sY < S::H1 - 1) {
@@ -717,14 +712,23 @@ __global__ __launch_bounds__(S::NTHREADS) void step2_kernel(const float* __restr
     s2[pos] = density(fr);
   }
   __syncthreads();
-  // (D) step t + 1 on the tile
+  // (D) step t + 1 on the tile; with kMid first the state of t + 1, f-bar_i
+  // of each tile node, which LDS holds where it streamed to
   const int x = x0 + lx;
   if (x >= nx) return;
   char* const ob = reinterpret_cast<char*>(dst) + (size_t)y0 * rowb;
+  char* const mb = kMid ? reinterpret_cast<char*>(mid) + (size_t)y0 * rowb : nullptr;
 #pragma unroll
   for (int k = 0; k < S::KD; ++k) {
     const int r = ly + k * S::WY;
     if (y0 + r >= ny) break;
+    if constexpr (kMid) {
+      const int pos = (r + 1) * S::LW + lx + 1;
+      const unsigned o = (unsigned)r * rb + 4u * (unsigned)x;
+#pragma unroll
+      for (int i = 0; i < 9; ++i)
+        __builtin_nontemporal_store(sg[i * S::G + pos + kCy[i] * S::LW + kCx[i]], reinterpret_cast<float*>(mb + i * pb + o));
+    }
     float gx, gy;
     stencil_at<S::LW>(s2, (r + 1) * S::LW + lx + 1, gx, gy);
     collide_node<float>(fd[k], rd[k], gx, gy, c);

@@ -147,7 +147,7 @@ def test_moments_fields_and_totals():
 @pytest.mark.parametrize("nx,ny,n", [(4096, 1024, 6), (1000, 700, 5), (2048 + 37, 1024 + 11, 7),
                                      (16384, 8192, 2)])
 def test_two_step_launches_match_single_steps(nx, ny, n):
-    """lbm_step(n) on lattices with at least one 64 x 16 tile per CU runs
+    """lbm_step(n) on lattices with at least one 64 x 24 tile per CU runs
     two steps per launch (interior tiles with 32-bit offsets, edge tiles
     with wrapped 64-bit addresses, ragged tiles, an odd remainder as one
     single step, and a state above 4 GiB): bitwise the result of n calls of
