@@ -145,13 +145,15 @@ def test_moments_fields_and_totals():
 
 
 @pytest.mark.parametrize("nx,ny,n", [(4096, 1024, 6), (1000, 700, 5), (2048 + 37, 1024 + 11, 7),
-                                     (16384, 8192, 2)])
+                                     (16384, 8192, 2), (16384, 1, 3), (20000, 9, 4), (7, 60000, 4),
+                                     (70, 9000, 3)])
 def test_two_step_launches_match_single_steps(nx, ny, n):
     """lbm_step(n) on lattices with at least one 64 x 24 tile per CU runs
     two steps per launch (interior tiles with 32-bit offsets, edge tiles
     with wrapped 64-bit addresses, ragged tiles, an odd remainder as one
-    single step, and a state above 4 GiB): bitwise the result of n calls of
-    lbm_step(1)."""
+    single step, a state above 4 GiB, and lattices thinner than the loaded
+    region, down to one row or seven columns, where it wraps more than
+    once): bitwise the result of n calls of lbm_step(1)."""
     _, co = params_pair(nx, ny, tr=0.7, width=10.0)
     rng = np.random.default_rng(nx + ny)
     rho = wl._f32(0.5 * (co.rho_g + co.rho_l) + rng.uniform(-0.01, 0.01, (ny, nx)))
