@@ -374,7 +374,7 @@ def fwd_adjoint_leg(pkg, wl, timer, torch, n=2048, steps=1000, every=100):
     (every = 1 keeps every state: no recomputation).  Timed on a second run,
     the first having allocated the checkpoint and segment buffers."""
     tr, width = 0.6, 10.0
-    need = (steps // every + every + 4) * 36 * n * n
+    need = (steps // every + 2 * every + 6) * 36 * n * n
     torch.cuda.empty_cache()
     free = torch.cuda.mem_get_info()[0]
     if need > 0.9 * free:

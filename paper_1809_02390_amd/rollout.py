@@ -21,8 +21,13 @@ forward's) and the adjoint steps run back through them
 
 applied by the library (lbm_adjoint_params).
 
-Device memory: ceil(n / every) + 1 checkpoints + (every - 1) segment states
-+ two adjoint states (11 fields each), all FP32 over nx*ny nodes.  With
+Backward with more than one segment: the recomputation of the next segment
+runs on a second context and stream while the adjoint steps run back
+through the current one (two sets of segment states, ordered by events).
+
+Device memory: ceil(n / every) + 1 checkpoints + 2 (every - 1) segment
+states and the second context's two state buffers (every - 1 with one
+segment) + two adjoint states (11 fields each), all FP32 over nx*ny nodes.  With
 every = 1 every state is kept and nothing is recomputed (the forward +
 adjoint then moves 54 + 124 instead of 36 + 54 + 124 bytes per node and
 step: the two-step kernel reads and writes each node's state once per two
@@ -39,14 +44,18 @@ import math
 
 import torch
 
-from .lbm import Lattice, lbm_adjoint_bytes, lbm_adjoint_params, lbm_adjoint_theta, lbm_checkpoint_bytes
+from .lbm import (Lattice, lbm_adjoint_bytes, lbm_adjoint_params, lbm_adjoint_run, lbm_adjoint_theta,
+                  lbm_checkpoint_bytes, lbm_step_saved_chain)
 
 
 def rollout_bytes(nsteps, every, state_bytes, adjoint_bytes):
     """Device bytes a Rollout holds besides the lattice's own buffers:
-    checkpoints, segment states and the two adjoint states."""
+    checkpoints, two sets of segment states (with more than one segment:
+    one recomputed while the adjoint runs through the other) and the A/B
+    buffers of the recomputing context, and the two adjoint states."""
     ckpt = -(-nsteps // every) + 1
-    pool = every - 1
+    nseg = -(-nsteps // every)
+    pool = 2 * (every - 1) + 2 if every > 1 and nseg > 1 else every - 1
     return (ckpt + pool) * state_bytes + 2 * adjoint_bytes
 
 
@@ -79,6 +88,8 @@ class Rollout:
         if nsteps < 0 or (every != "auto" and int(every) < 1):
             raise ValueError("nsteps >= 0 and every >= 1 (or 'auto') are required")
         self.lat = Lattice(nx, ny, device=device, **kw)
+        self.kw = kw
+        self.rec = None  # context recomputing segments on a stream of its own (backward)
         if every == "auto":
             every = choose_every(int(nsteps), lbm_checkpoint_bytes(self.lat.params),
                                  lbm_adjoint_bytes(self.lat.params), free_device_bytes(self.lat.f_a.device))
@@ -86,6 +97,7 @@ class Rollout:
         self.starts = list(range(0, self.nsteps, self.every))
         self.ckpt = [None] * (len(self.starts) + 1)  # states at the starts, then the final state
         self.pool = []  # segment states beyond the checkpoint (backward)
+        self.pools = ([], [])  # the same, two sets (backward with more than one segment)
         self.inputs = None
 
     def _conv(self, a):
@@ -128,10 +140,61 @@ class Rollout:
         lat = self.lat
         lbm_adjoint_theta(lat.ctx, read=False, reset=True)
         a, b = lat.adjoint_seed(lam_T), lat.adjoint_buffer()
+        if len(self.starts) > 1 and self.every > 1:
+            return self._backward_overlapped(a, b)
         for s in reversed(range(len(self.starts))):
             out = lat.adjoint_run(self._segment_states(s), a, b)
             if out is b:
                 a, b = b, a
+        return a
+
+    def _backward_overlapped(self, a, b):
+        """The adjoint sweep with the recomputation of segment s - 1 on a
+        second context and stream while the adjoint steps run back through
+        segment s: two sets of segment states alternate, ordered by events
+        (a set is recomputed only after the adjoint that read it, the adjoint
+        of a segment only after its recomputation).  The same library calls
+        in the same order per stream as the sequential sweep, so the same
+        bits."""
+        lat = self.lat
+        dev = lat.f_a.device
+        cur, main = torch.cuda.current_stream(dev), lat.stream
+        if self.rec is None:
+            self.rec = Lattice(self.nx, self.ny, device=dev, stream=torch.cuda.Stream(dev), **self.kw)
+        side = self.rec.stream
+        for pool in self.pools:
+            while len(pool) < self.every - 1:
+                pool.append(lat.checkpoint_buffer())
+        main.wait_stream(cur)
+        side.wait_stream(main)  # checkpoints written, segment buffers allocated
+        sb, ab = lbm_checkpoint_bytes(lat.params), lbm_adjoint_bytes(lat.params)
+        ready, free = {}, [None, None]
+
+        def recompute(s):
+            k = s % 2
+            if free[k] is not None:
+                side.wait_event(free[k])  # the adjoint that read this set has run
+            m = min(self.every, self.nsteps - self.starts[s])
+            states = [self.ckpt[s]] + self.pools[k][:m - 1]
+            if m > 1:
+                lbm_step_saved_chain(self.rec.ctx, states, sb)
+            ev = torch.cuda.Event()
+            ev.record(side)
+            ready[s] = (ev, states)
+
+        recompute(len(self.starts) - 1)
+        for s in reversed(range(len(self.starts))):
+            if s > 0:
+                recompute(s - 1)
+            ev, states = ready.pop(s)
+            main.wait_event(ev)
+            if lbm_adjoint_run(lat.ctx, states, a, b, sb, ab) == 1:
+                a, b = b, a
+            fe = torch.cuda.Event()
+            fe.record(main)
+            free[s % 2] = fe
+        main.wait_stream(side)
+        cur.wait_stream(main)
         return a
 
     def backward(self, grad_rho_T):
@@ -147,8 +210,13 @@ class Rollout:
         return drho0, dth, dp
 
     def release(self):
+        if self.rec is not None:
+            torch.cuda.current_stream(self.lat.f_a.device).wait_stream(self.rec.stream)
+            self.rec.close()
+            self.rec = None
         self.ckpt = [None] * (len(self.starts) + 1)
         self.pool = []
+        self.pools = ([], [])
         self.lat.close()
 
 

@@ -10,8 +10,9 @@ SB, AB = 9 * 512 * 512 * 4, 11 * 512 * 512 * 4  # state and adjoint bytes of a 5
 
 def test_rollout_bytes_counts_checkpoints_pool_and_adjoints():
     assert rollout_bytes(2000, 1, SB, AB) == 2001 * SB + 2 * AB
-    assert rollout_bytes(2000, 100, SB, AB) == (20 + 1 + 99) * SB + 2 * AB
-    assert rollout_bytes(7, 2, SB, AB) == (4 + 1 + 1) * SB + 2 * AB
+    assert rollout_bytes(2000, 100, SB, AB) == (20 + 1 + 2 * 99 + 2) * SB + 2 * AB
+    assert rollout_bytes(7, 2, SB, AB) == (4 + 1 + 2 * 1 + 2) * SB + 2 * AB
+    assert rollout_bytes(50, 100, SB, AB) == (1 + 1 + 99) * SB + 2 * AB  # one segment: one set
 
 
 def test_every_state_kept_when_it_fits():
