@@ -366,3 +366,27 @@ def test_droplet512_gradient_matches_stored_oracle_derivatives():
         errs[name] = abs(v - e["value"]) / abs(e["value"])
     print("relative errors:", errs)
     assert max(errs.values()) <= 1e-4, errs
+
+
+def test_overlapped_backward_matches_sequential_sweep():
+    """The backward sweep with the next segment recomputed on a second
+    stream (four segments, the last one short) gives bitwise the adjoint
+    state and the dL/d theta sums of the sweep that recomputes each segment
+    on the lattice's own stream right before its adjoint steps."""
+    nx, ny, steps, every = 300, 200, 35, 10
+    _, co = params_pair(nx, ny, tr=0.7, width=10.0)
+    rho = wl.droplets(nx, ny, co.rho_g, co.rho_l, co.width, [(120, 100), (200, 90)], [40.0, 35.0])
+    r = pkg.Rollout(nx, ny, steps, every, tr=0.7, width=10.0)
+    r.forward(torch.tensor(rho, device="cuda"))
+    lam = torch.randn((9, ny, nx), device="cuda", generator=torch.Generator(device="cuda").manual_seed(5))
+    lat = r.lat
+    got = lat.adjoint_get(r.backward_state(lam)).clone()
+    th_got = lat.adjoint_theta(reset=True)
+    a, b = lat.adjoint_seed(lam), lat.adjoint_buffer()
+    for s in reversed(range(len(r.starts))):
+        if lat.adjoint_run(r._segment_states(s), a, b) is b:
+            a, b = b, a
+    ref = lat.adjoint_get(a)
+    th_ref = lat.adjoint_theta(reset=True)
+    assert r.rec is not None and torch.equal(got, ref) and np.array_equal(np.array(th_got), np.array(th_ref))
+    r.release()
