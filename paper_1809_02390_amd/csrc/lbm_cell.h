@@ -179,24 +179,46 @@ __host__ __device__ __forceinline__ NodeState<T> node_state(T rho, T jx, T jy, T
 // and for the T and X terms (T . g + dp X . g is one coefficient per
 // monomial and row).  g is the stencil gradient (= grad rho, supplement
 // Eq. 61); grad p_LBE = dp_lbe g.
-template <typename T>
+//
+// kFewerOps: three fewer instructions per node (F_m2 from hF8, 3 u_x u_y
+// shared by F_m4, F_m6 and 9 u_x^2 u_y^2 = (3 u_x u_y)^2, the factor 3 of
+// F . u folded into its fused multiply-adds), in longer chains of dependent
+// instructions: faster where many waves hide them (the 2-byte steps), slower
+// in the two-step FP32 kernel.  The FP32 kernels keep the other form, which
+// both of them share bit for bit.
+template <typename T, bool kFewerOps = false>
 __host__ __device__ __forceinline__ void collide_scaled(const T* m, const NodeState<T>& s, T gx, T gy,
                                                         const Coef<T>& c, T* w) {
 #pragma clang fp contract(off)
   const T rho = s.rho, ux = s.ux, uy = s.uy, Fx = s.Fx, Fy = s.Fy, dp = s.dp_lbe;
   const T ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy, u2 = ux2 + uy2, dxy = ux2 - uy2;
   const T c3x = ux * ux2, c3y = uy * uy2, cxyy = uxy * uy, cxxy = uxy * ux;
-  // half force moments (main Eq. 4; hF8 = 2 F_m8 / 2)
-  const T Fxu = Fx * ux, Fyu = Fy * uy;
-  const T Fu3 = T(3) * (Fxu + Fyu);
-  const T hF2 = fma_(T(9), fma_(Fx, cxyy, Fy * cxxy), -Fu3);
-  const T hF4 = fma_(Fx, fma_(T(1.5), uy2, T(-0.5)), T(3) * Fy * uxy);
-  const T hF6 = fma_(Fy, fma_(T(1.5), ux2, T(-0.5)), T(3) * Fx * uxy);
-  const T hF7 = Fxu - Fyu;
-  const T hF8 = fma_(Fx, uy, Fy * ux);
+  // half force moments (main Eq. 4; hF8 = 2 F_m8 / 2; with kFewerOps
+  // F_x u_x u_y^2 + F_y u_x^2 u_y = u_x u_y hF8, Fu = F_m1 / 6) and
   // (1) d = m - m^eq + F_m/2 with the equilibrium moments of main Eq. 3
-  const T meq2 = fma_(rho, fma_(T(9) * ux2, uy2, T(-3) * u2), fma_(c.alpha2, rho, c.beta2 * s.eta));
-  const T d1 = fma_(T(-3) * rho, u2, fma_(T(-2), s.eta - rho, m[1])) + Fu3;
+  // (kFewerOps: 9 u_x^2 u_y^2 = (3 u_x u_y)^2)
+  const T Fxu = Fx * ux, Fyu = Fy * uy;
+  T Fu3 = T(0), Fu = T(0), hF2, hF4, hF6, hF7, hF8, meq2, d1;
+  if constexpr (!kFewerOps) {
+    Fu3 = T(3) * (Fxu + Fyu);
+    hF2 = fma_(T(9), fma_(Fx, cxyy, Fy * cxxy), -Fu3);
+    hF4 = fma_(Fx, fma_(T(1.5), uy2, T(-0.5)), T(3) * Fy * uxy);
+    hF6 = fma_(Fy, fma_(T(1.5), ux2, T(-0.5)), T(3) * Fx * uxy);
+    hF7 = Fxu - Fyu;
+    hF8 = fma_(Fx, uy, Fy * ux);
+    meq2 = fma_(rho, fma_(T(9) * ux2, uy2, T(-3) * u2), fma_(c.alpha2, rho, c.beta2 * s.eta));
+    d1 = fma_(T(-3) * rho, u2, fma_(T(-2), s.eta - rho, m[1])) + Fu3;
+  } else {
+    Fu = Fxu + Fyu;
+    const T uxy3 = T(3) * uxy;
+    hF8 = fma_(Fx, uy, Fy * ux);
+    hF2 = fma_(T(-3), Fu, (T(3) * uxy3) * hF8);
+    hF4 = fma_(Fx, fma_(T(1.5), uy2, T(-0.5)), uxy3 * Fy);
+    hF6 = fma_(Fy, fma_(T(1.5), ux2, T(-0.5)), uxy3 * Fx);
+    hF7 = Fxu - Fyu;
+    meq2 = fma_(rho, fma_(uxy3, uxy3, T(-3) * u2), fma_(c.alpha2, rho, c.beta2 * s.eta));
+    d1 = fma_(T(3), Fu, fma_(T(-3) * rho, u2, fma_(T(-2), s.eta - rho, m[1])));
+  }
   const T d2 = m[2] - meq2 + hF2;
   const T d4 = fma_(-rho, fma_(T(3), cxyy, -ux), m[4]) + hF4;
   const T d6 = fma_(-rho, fma_(T(3), cxxy, -uy), m[6]) + hF6;
@@ -210,7 +232,11 @@ __host__ __device__ __forceinline__ void collide_scaled(const T* m, const NodeSt
   // (6) S Q_m, each row times its factor of D
   const T gg = fma_(gx, gx, gy * gy);
   const T b1 = fma_(dp, c.w_x1, c.w_t1b), b7 = fma_(dp, c.w_x7, c.w_t7b), b8 = fma_(dp, c.w_x8, c.w_t8);
-  T a = T(2.0 / 36.0) * ((D1 - d1) + Fu3);
+  T a;
+  if constexpr (kFewerOps)
+    a = T(2.0 / 36.0) * fma_(T(3), Fu, D1 - d1);
+  else
+    a = T(2.0 / 36.0) * ((D1 - d1) + Fu3);
   a = fma_(c.w_r11 * u2, D1, a);
   a = fma_(c.w_r17 * dxy, D7, a);
   a = fma_(c.w_r18 * uxy, D8, a);
@@ -253,12 +279,12 @@ __host__ __device__ __forceinline__ void add_transpose_moments(const T* w, T* f)
 
 // f-bar from pre-collision f at one node of density rho (density(f)), given
 // the stencil gradient g.
-template <typename T>
+template <typename T, bool kFewerOps = false>
 __host__ __device__ __forceinline__ void collide_node(T* f, T rho, T gx, T gy, const Coef<T>& c) {
   T m[9], w[9];
   forward_moments(f, m);
   const NodeState<T> s = node_state(rho, m[3], m[5], gx, gy, c);
-  collide_scaled(m, s, gx, gy, c, w);
+  collide_scaled<T, kFewerOps>(m, s, gx, gy, c, w);
   add_transpose_moments(w, f);
 }
 

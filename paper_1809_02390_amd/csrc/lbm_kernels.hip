@@ -523,7 +523,7 @@ __global__ __launch_bounds__(S::NTHREADS) void step_kernel(const void* __restric
     neighbours<S>(srho, threadIdx.x + 1, ly + 1, nb);
     float gx, gy;
     stencil(nb[1], nb[2], nb[3], nb[4], nb[5], nb[6], nb[7], nb[8], gx, gy);
-    collide_node<float>(f[k], rho[k], gx, gy, c);
+    collide_node<float, St::kRef>(f[k], rho[k], gx, gy, c);
     E out[9];
     if constexpr (St::kRef) {
       // f-bar_i streams to x + e_i: encode it against that node's reference
