@@ -1445,11 +1445,16 @@ void launch_step(const lbm_ctx* ctx, const void* src, void* dst, const uint16_t*
 
 // Two FP32 steps per launch (step2_kernel) on lattices with at least one
 // of its tiles per CU; smaller lattices take single steps on smaller tiles.
+// Its interior tiles address TY + 8 rows of 36 nx bytes from one base with
+// 32-bit offsets, which bounds the width (about 3.7M nodes); wider lattices
+// take single steps too.
 #ifndef LBM_FUSE_STEPS
 #define LBM_FUSE_STEPS 1
 #endif
 bool use_step2(const lbm_ctx* ctx) {
-  return LBM_FUSE_STEPS && ctx->p.storage == LBM_FP32 && tiles_total<Step2Tile>(ctx->p.nx, ctx->p.ny) >= ctx->cus;
+  const unsigned long long band = 36ull * (unsigned long long)ctx->p.nx * (Step2Tile::TY + 8);
+  return LBM_FUSE_STEPS && ctx->p.storage == LBM_FP32 && band < (1ull << 32) &&
+         tiles_total<Step2Tile>(ctx->p.nx, ctx->p.ny) >= ctx->cus;
 }
 
 // src (time t) -> dst (time t + 2), and mid (time t + 1) if kMid.
