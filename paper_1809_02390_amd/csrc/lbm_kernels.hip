@@ -1405,6 +1405,12 @@ void for_tile_rows(int nx, int ny, Fn&& fn) {
   const int nty = (ny + S::TY - 1) / S::TY;
   if constexpr (kFP32) {
     if (wide_state(nx, ny, 4)) {
+      // a band of TY + 4 rows must fit 32-bit offsets (lattices up to about
+      // 9M nodes wide); wider ones take 64-bit addresses on every tile row
+      if (36ull * (unsigned long long)nx * (S::TY + 4) >= (1ull << 32)) {
+        fn(std::integral_constant<int, kWide>{}, TileRows{0, nty, 0}, nty);
+        return;
+      }
       int lo, hi;
       band_rows<S>(ny, lo, hi);
       if (hi > lo) fn(std::integral_constant<int, kBand>{}, TileRows{lo, hi - lo, 0}, hi - lo);

@@ -371,6 +371,30 @@ def test_sampled_parity_at_the_row_layout_limit(nx, ny):
     assert np.abs(got - ref).max() / co.rho_l <= TOL
 
 
+@pytest.mark.parametrize("nx,ny", [(4_000_000, 59), (11_000_000, 21)])
+def test_sampled_parity_widest_lattices(nx, ny):
+    """Lattices near the node limit (9 nx ny < 2^31) in extreme aspect: at
+    4M nodes wide the two-step kernel's 32-bit band offsets would not fit
+    (single steps; the one-step kernel's band rows do), at 11M wide neither
+    does and every tile row takes 64-bit addresses.  Spinodal field, 5
+    steps, sampled nodes against oracle crops."""
+    steps = 5
+    assert 9 * nx * ny < 2 ** 31 and 36 * nx * ny >= 2 ** 32
+    _, co = params_pair(nx, ny, tr=0.7, width=10.0)
+    rho = wl.uniform_noise(nx, ny, 0.5 * (co.rho_g + co.rho_l), 0.01, seed=ny)
+    lat = lattice(nx, ny, rho, tr=0.7, width=10.0)
+    lat.step(steps)
+    pts = [(nx - 1, ny - 1), (0, ny - 1), (nx // 2, ny - 2), (0, 0), (nx - 1, 0), (777, ny // 2),
+           (nx - 17, ny - 3), (3_999_999 % nx, 8), (255, 7), (nx - 300, 12)]
+    ref = sampled_oracle(co, rho, pts, steps)
+    del rho
+    st = lat.state()
+    got = device_samples(st, pts)
+    del st
+    lat.close()
+    assert np.abs(got - ref).max() / co.rho_l <= TOL
+
+
 def test_two_lattices_on_two_streams_match_single_runs():
     """Every launch goes to its context's stream and contexts share no device
     state: two lattices (FP32 and FP16) stepped in turn on two streams end
