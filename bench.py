@@ -173,12 +173,14 @@ class Timer:
         return a.elapsed_time(b)  # ms
 
 
-def make_pacer(pkg, wl, n=4096, tr=0.7, width=10.0):
+def make_pacer(pkg, wl, nx=4096, ny=4080, tr=0.7, width=10.0):
     """The lattice whose steps make the lead-in of every timed region (an
-    FP32 4096^2 spinodal state of its own, seed 4)."""
-    d = pkg.lbm_derive(pkg.make_params(n, n, tr=tr, width=width))
-    return pkg.Lattice(n, n, tr=tr, width=width).init(
-        wl.spinodal({"rho_g": d.rho_g, "rho_l": d.rho_l, "width": width}, n=n, seed=4))
+    FP32 spinodal state of its own, seed 4).  16 rows fewer than the 4096^2
+    workload: the same work per step within 0.4 %, but another launch grid,
+    so a kernel trace keeps its steps apart from the timed ones."""
+    d = pkg.lbm_derive(pkg.make_params(nx, ny, tr=tr, width=width))
+    rho = wl.uniform_noise(nx, ny, 0.5 * (d.rho_g + d.rho_l), 0.01, seed=4)
+    return pkg.Lattice(nx, ny, tr=tr, width=width).init(rho)
 
 
 def step_leg(pkg, wl, timer, storage, n, steps, warmup, tr=0.7, width=10.0, single=False):
@@ -574,7 +576,7 @@ def main():
         "roofline": headline_roofline(fp32),
         "legs": legs,
         "wall_s_fp32_leg": round(t_wall, 3),
-        "lead_in": {"steps": timer.lead_in_steps, "lattice": "4096x4096 FP32, its own spinodal state",
+        "lead_in": {"steps": timer.lead_in_steps, "lattice": "4096x4080 FP32, its own spinodal state",
                     "note": "untimed steps of another lattice enqueued right before each timed region"},
         "paper_figures": {"relative_cost_vs_pseudopotential_mrt": 1.178,
                           "source": "supplement Sec. IV: cost of the model relative to the pseudopotential MRT "
