@@ -390,3 +390,22 @@ def test_overlapped_backward_matches_sequential_sweep():
     th_ref = lat.adjoint_theta(reset=True)
     assert r.rec is not None and torch.equal(got, ref) and np.array_equal(np.array(th_got), np.array(th_ref))
     r.release()
+
+
+def test_recomputed_segments_are_bitwise_the_forward_pass():
+    """On a lattice that takes two steps per launch, the backward's
+    recomputation of each checkpoint segment (lbm_step_saved_chain, storing
+    every state) continues into the next checkpoint the forward pass saved
+    (lbm_step, no state between its two steps): the same bits."""
+    nx, ny, steps, every = 1024, 384, 40, 10
+    _, co = params_pair(nx, ny, tr=0.7, width=10.0)
+    rho = wl.droplets(nx, ny, co.rho_g, co.rho_l, co.width, [(300, 190), (700, 180)], [60.0, 50.0])
+    r = pkg.Rollout(nx, ny, steps, every, tr=0.7, width=10.0)
+    r.forward(torch.tensor(rho, device="cuda"))
+    lat = r.lat
+    nxt = lat.checkpoint_buffer()
+    for s in range(len(r.starts)):
+        states = r._segment_states(s)
+        lat.step_saved(states[-1], nxt)
+        assert torch.equal(fp32_state_of(nxt, nx, ny), fp32_state_of(r.ckpt[s + 1], nx, ny)), s
+    r.release()
