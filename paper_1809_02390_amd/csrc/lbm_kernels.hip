@@ -619,7 +619,9 @@ __global__ __launch_bounds__(S::NTHREADS) void step2_kernel(const float* __restr
   __shared__ float s1[S::W1 * S::H1];  // densities at t of the loaded region; then at t + 1 of tile + ring
   __shared__ float sg[9 * S::G];       // populations arriving at the tile and its ring at t + 1
   const size_t rowb = (size_t)36 * nx;  // bytes from one lattice row of a state to the next
-  const unsigned rb = 36u * (unsigned)nx, pb = 4u * (unsigned)nx;  // same; from one population to the next
+  // rb: the same in 32 bits (offsets within a tile's rows); pb: bytes from
+  // one population of a row to the next
+  const unsigned rb = 36u * (unsigned)nx, pb = 4u * (unsigned)nx;
   int tx, ty;
   strip_tile(xcd_tile(blockIdx.x, ntiles), ntx, ntiles / ntx, strip, tx, ty);
   const int x0 = tx * S::TX, y0 = ty * S::TY;
