@@ -109,6 +109,31 @@ def test_adjoint_params_apply_the_parameter_jacobian(case):
     assert lat.adjoint_theta(reset=True) == (0.0, 0.0, 0.0)
 
 
+def test_adjoint_step_nondefault_parameters():
+    """One adjoint step with every problem parameter away from its default
+    (s_p, s_eps, varpi, a, b, R, T_r, sigma given, W) on 200 x 35, against
+    the oracle's complex-step derivatives.  Putting any one of s_p, s_eps,
+    varpi, b, T_r, sigma or W back to its default moves lambda^t by >= 2.2e-2
+    of max |lambda|; a moves dL/dtheta (theta's K' and R T scale with it)."""
+    kw = dict(s_p=0.8, s_eps=1.4, varpi=0.12, a=0.5, b=2.5, r_gas=1.5, tr=0.85, sigma=0.0021, width=12.0)
+    nx, ny = 200, 35
+    _, co = params_pair(nx, ny, **kw)
+    f = nonequilibrium_state(nx, ny, co, 5)
+    lam = f32(np.random.default_rng(6).standard_normal(f.shape))
+    lat = pkg.Lattice(nx, ny, **kw).set_state(f)
+    ck = lat.save_state()
+    a, b = lat.adjoint_seed(lam), lat.adjoint_buffer()
+    lat.adjoint_theta(reset=True)
+    lat.adjoint_step(ck, a, b)
+    got = lat.adjoint_get(b).double().cpu().numpy()
+    ref = adj.step_vjp(f, lam, co)
+    assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
+    dth = np.array(lat.adjoint_theta(reset=True))
+    ref_th = adj.step_param_vjp(f, lam, co)
+    scale = param_term_scale(f, lam, co)
+    assert np.all(np.abs(dth - ref_th) <= 1e-5 * scale), (dth, ref_th, scale)
+
+
 @pytest.mark.parametrize("nx,ny", [(4096, 4096), (16384, 8192)])
 def test_adjoint_step_sampled(nx, ny):
     """One adjoint step on a spinodal field (mean of the coexistence

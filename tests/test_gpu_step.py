@@ -187,6 +187,34 @@ def test_two_step_chain_matches_single_steps():
     assert torch.equal(state(alternating[-1]), state(single[-1]))
 
 
+# Every problem parameter away from its default: s_p and varpi (with s_q,
+# s_e and the model coefficients they set, main Eqs. 7 and 16), s_eps given
+# instead of s_e, b and T_r of the Carnahan-Starling EOS, sigma given
+# instead of the sound-speed rule, and W.  In the oracle, putting any one of
+# s_p, s_eps, varpi, b, T_r, sigma or W of this set back to its default
+# moves some population of the 200 x 70 droplet after 6 steps by
+# >= 1.6e-3 rho_l, 160 times the bound.  a and R change nothing at a given
+# sigma (K_EOS absorbs them: the oracle's states agree bitwise).
+NONDEFAULT = dict(s_p=0.8, s_eps=1.4, varpi=0.12, a=0.5, b=2.5, r_gas=1.5, tr=0.85, sigma=0.0021, width=12.0)
+
+
+@pytest.mark.parametrize("nx,ny", [(200, 70), (1024, 384)])
+def test_step_parity_nondefault_parameters(nx, ny):
+    """Parity at NONDEFAULT on a lattice run one step per launch (200 x 70)
+    and on one run two steps per launch (1024 x 384: one 64 x 24 tile per
+    CU), after 1 and after 6 steps."""
+    _, co = params_pair(nx, ny, **NONDEFAULT)
+    rho = wl.droplets(nx, ny, co.rho_g, co.rho_l, co.width, [(nx * 0.45, ny * 0.55)], [min(nx, ny) * 0.3])
+    rng = np.random.default_rng(nx)
+    ux, uy = (wl._f32(rng.uniform(-0.02, 0.02, (ny, nx))) for _ in range(2))
+    lat = lattice(nx, ny, rho, ux, uy, **NONDEFAULT)
+    f = oracle_init(co, rho, ux, uy)
+    for chunk in (1, 5):
+        lat.step(chunk)
+        f = lbm.run(f, co, chunk)
+        compare(lat, f, co)
+
+
 def test_deterministic():
     co, rho, ux, uy = droplet_case(96, 80, seed=4)
     a = lattice(96, 80, rho, ux, uy, tr=0.8)

@@ -101,6 +101,29 @@ def test_ragged_lattice_runs_and_matches_fp32(storage, nx, ny):
     assert err <= STEP_TOL[storage], err
 
 
+@pytest.mark.parametrize("storage", STORAGES)
+def test_nondefault_parameters_within_storage_precision(storage):
+    """Every problem parameter away from its default (s_p, s_eps, varpi,
+    a, b, R, T_r, sigma given, W) on a 200 x 70 droplet: after 6 steps every
+    population within the storage bound of the oracle.  Putting any one of
+    them back to its default moves the oracle's state by >= 1.7e-3 rho_l
+    (a and R: by nothing, K_EOS absorbs them), above both bounds."""
+    kw = dict(s_p=0.8, s_eps=1.4, varpi=0.12, a=0.5, b=2.5, r_gas=1.5, tr=0.85, sigma=0.0021, width=12.0)
+    nx, ny = 200, 70
+    _, co = params_pair(nx, ny, **kw)
+    rho = wl.droplets(nx, ny, co.rho_g, co.rho_l, co.width, [(90, 38)], [21.0])
+    rng = np.random.default_rng(7)
+    ux, uy = (wl._f32(rng.uniform(-0.02, 0.02, (ny, nx))) for _ in range(2))
+    lat = lattice(nx, ny, rho, ux, uy, storage=storage, **kw)
+    lat.step(6)
+    ref = lbm.run(oracle_init(co, rho, ux, uy), co, 6)
+    got = lat.state().double().cpu().numpy()
+    err_f = np.abs(got - ref).max() / co.rho_l
+    err_r = np.abs(got.sum(0) - ref.sum(0)).max() / co.rho_l
+    print(f"{storage}: max |d f| / rho_l = {err_f:.2e}, max |d rho| / rho_l = {err_r:.2e}")
+    assert err_r <= STEP_TOL[storage] and err_f <= STEP_TOL[storage], (err_r, err_f)
+
+
 @pytest.mark.parametrize("storage", ["fp32"] + STORAGES)
 def test_coexistence_error(storage):
     """Flat interface relaxed for 20000 steps at T_r = 0.7: coexistence
