@@ -218,6 +218,37 @@ def step_leg(pkg, wl, timer, storage, n, steps, warmup, tr=0.7, width=10.0, sing
                      "traffic": traffic, "alu": alu_roofline(kernel, n * n, mlups)}
 
 
+def graph_leg(pkg, wl, timer, torch, n, m=100, reps=20, tr=0.7, width=10.0):
+    """Small FP32 lattices, where launches rather than HBM or the ALU set
+    the time per step: lbm_step(m * reps) in one call against a HIP graph of
+    lbm_step(m), captured on the lattice's stream, replayed reps times."""
+    d = pkg.lbm_derive(pkg.make_params(n, n, tr=tr, width=width))
+    rho0 = wl.spinodal({"rho_g": d.rho_g, "rho_l": d.rho_l, "width": width}, n=n)
+    s = torch.cuda.Stream()
+    lat = pkg.Lattice(n, n, stream=s, tr=tr, width=width).init(rho0)
+    ms_eager = timer(lambda: lat.step(m * reps), pre=lambda: lat.step(m))
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        pkg.lbm.lbm_step(lat.ctx, m)
+    torch.cuda.synchronize()
+
+    def replays():
+        for _ in range(reps):
+            g.replay()
+
+    ms_graph = timer(replays, pre=g.replay)
+    tot = lat.moments(fields=False)
+    del g
+    lat.close()
+    if not all(np.isfinite(tot)):
+        raise RuntimeError(f"{n}^2 graph leg diverged")
+    lu = n * n * m * reps
+    eager, graph = lu / (ms_eager * 1e-3) / 1e6, lu / (ms_graph * 1e-3) / 1e6
+    return {"lattice": f"{n}x{n} FP32 spinodal", "steps_per_graph": m, "replays": reps,
+            "eager_mlups": round(eager, 1), "graph_mlups": round(graph, 1), "ratio": round(graph / eager, 4)}
+
+
 def _semi_axis(profile, level):
     """Half the distance between the outer level crossings of a 1-D profile."""
     i = np.where(profile > level)[0]
@@ -543,6 +574,8 @@ def main():
             leg["coexistence"] = coexistence_leg(pkg, wl, st)
             legs[st] = leg
             done(f"{st} step leg")
+        legs["graph_replay"] = [graph_leg(pkg, wl, timer, torch, k) for k in (256, 1024)]
+        done("graph replay legs")
         legs["fp32_coexistence"] = coexistence_leg(pkg, wl, "fp32")
         legs["coalescence_16384x8192"] = coalescence_legs(pkg, wl, timer)
         done("16384x8192 legs")

@@ -164,7 +164,15 @@ int lbm_get_state(lbm_ctx* ctx, float* f);
  * kernel launch (the state between them is never written), then one for an
  * odd remainder; every node is updated by the same operations as in a
  * single step, so the result is bitwise that of n calls with n = 1.  The
- * 2-byte storages take one step per launch. */
+ * 2-byte storages take one step per launch.
+ * The call only launches kernels on the context's stream (no allocation,
+ * copy or synchronisation), so it can be captured into a HIP graph on that
+ * stream.  A graph replays the launches with the A/B buffers they were
+ * recorded with, while the context switches buffers once per launch when
+ * the call is made: capture n a multiple of 4, which ends on the buffer it
+ * started from for every storage and launch shape, and each replay then
+ * advances the state by n steps (the step counter counts the captured call
+ * only). */
 int lbm_step(lbm_ctx* ctx, int32_t n);
 
 /* Macroscopic fields at the current time: rho = sum_i f_i and
