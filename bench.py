@@ -42,6 +42,9 @@ Prints one JSON line:
                      against the linear capillary mode;
   legs.head_on_collision  liquid bodies over time in head-on collisions of
                      two droplets at the paper's four (We, Re) pairs;
+  legs.graph_replay  256^2 and 1024^2, where launches set the time per step:
+                     lbm_step(2000) against a HIP graph of lbm_step(100)
+                     captured by the caller and replayed 20 times;
   cpu_baseline       the FP64 oracle timed on a bounded crop.
 """
 from __future__ import annotations
@@ -221,12 +224,15 @@ def step_leg(pkg, wl, timer, storage, n, steps, warmup, tr=0.7, width=10.0, sing
 def graph_leg(pkg, wl, timer, torch, n, m=100, reps=20, tr=0.7, width=10.0):
     """Small FP32 lattices, where launches rather than HBM or the ALU set
     the time per step: lbm_step(m * reps) in one call against a HIP graph of
-    lbm_step(m), captured on the lattice's stream, replayed reps times."""
+    lbm_step(m), captured on the lattice's stream, replayed reps times on
+    torch's current stream, where the eager calls run too."""
     d = pkg.lbm_derive(pkg.make_params(n, n, tr=tr, width=width))
     rho0 = wl.spinodal({"rho_g": d.rho_g, "rho_l": d.rho_l, "width": width}, n=n)
+    eager_lat = pkg.Lattice(n, n, tr=tr, width=width).init(rho0)
+    ms_eager = timer(lambda: eager_lat.step(m * reps), pre=lambda: eager_lat.step(m))
+    eager_lat.close()
     s = torch.cuda.Stream()
     lat = pkg.Lattice(n, n, stream=s, tr=tr, width=width).init(rho0)
-    ms_eager = timer(lambda: lat.step(m * reps), pre=lambda: lat.step(m))
     g = torch.cuda.CUDAGraph()
     torch.cuda.synchronize()
     with torch.cuda.graph(g, stream=s):
