@@ -159,12 +159,14 @@ int lbm_get_state(lbm_ctx* ctx, float* f);
 /* Advance n >= 0 time steps of main Eq. 13 with the force of main Eq. 12
  * (the collision by the six steps of supplement Sec. IV), alternating A
  * and B.  Each step fuses the
- * density halo, the force, the collision and the streaming.  LBM_FP32 on
- * lattices with at least one 64 x 24 tile per compute unit: two steps per
- * kernel launch (the state between them is never written), then one for an
- * odd remainder; every node is updated by the same operations as in a
- * single step, so the result is bitwise that of n calls with n = 1.  The
- * 2-byte storages take one step per launch.
+ * density halo, the force, the collision and the streaming.  LBM_FP32
+ * (lattices up to about 3.7M nodes wide): two steps per kernel launch (the
+ * state between them is never written) on tiles of 64 x 24 nodes, or of
+ * 64 x 16 or 32 x 8 where the larger ones give fewer tiles than the device
+ * has compute units, then one step for an odd remainder; every node is
+ * updated by the same operations as in a single step, so the result is
+ * bitwise that of n calls with n = 1.  The 2-byte storages take one step
+ * per launch.
  * The call only launches kernels on the context's stream (no allocation,
  * copy or synchronisation), so it can be captured into a HIP graph on that
  * stream.  A graph replays the launches with the A/B buffers they were
@@ -225,9 +227,10 @@ int lbm_step_saved(lbm_ctx* ctx, const void* src, void* dst);
 /* n steps from checkpoint to checkpoint: bufs[j+1] := step(bufs[j]) for
  * j = 0 .. n-1 (a host array of n+1 device checkpoint buffers, consecutive
  * ones distinct), bitwise as lbm_step_saved.  Where bufs[j+2] is not
- * bufs[j], the steps j and j+1 run as one launch of the two-step kernel of
- * lbm_step that also writes bufs[j+1] (all n+1 buffers distinct: every pair
- * does).  One call recomputes a checkpoint segment.  LBM_FP32 only. */
+ * bufs[j] and lbm_step takes two steps per launch, the steps j and j+1 run
+ * as one launch of its two-step kernel that also writes bufs[j+1] (all n+1
+ * buffers distinct: every pair does).  One call recomputes a checkpoint
+ * segment.  LBM_FP32 only. */
 int lbm_step_saved_chain(lbm_ctx* ctx, void* const* bufs, int32_t n);
 
 /* ---- Adjoint (reverse mode) of a rollout; LBM_FP32 storage only ---------

@@ -1388,8 +1388,6 @@ int strip_width(int nx, int tx, bool raster) {
 template <class S>
 int tiles_total(int nx, int ny) { return tiles_x<S>(nx) * ((ny + S::TY - 1) / S::TY); }
 
-// One step of storage St with tile shape S from the buffer src (and its
-// reference plane) to dst, on the context's stream.
 // Tile rows [lo, hi) whose reads stay inside the lattice (t TY >= 2 and
 // t TY + TY + 2 <= ny): the kBand launch of a wide state.
 template <class S>
@@ -1423,6 +1421,8 @@ void for_tile_rows(int nx, int ny, Fn&& fn) {
   fn(std::integral_constant<int, kAbs>{}, TileRows{0, nty, 0}, nty);
 }
 
+// One step of storage St with tile shape S from the buffer src (and its
+// reference plane) to dst, on the context's stream.
 template <class St, class S>
 void launch_step_tiles(const lbm_ctx* ctx, const void* src, void* dst, const uint16_t* ref_in, uint16_t* ref_out) {
   const int nx = ctx->p.nx, ny = ctx->p.ny, ntx = tiles_x<S>(nx);
@@ -1451,28 +1451,49 @@ void launch_step(const lbm_ctx* ctx, const void* src, void* dst, const uint16_t*
   launch_step_tiles<St, SmallTile>(ctx, src, dst, ref_in, ref_out);
 }
 
-// Two FP32 steps per launch (step2_kernel) on lattices with at least one
-// of its tiles per CU; smaller lattices take single steps on smaller tiles.
-// Its interior tiles address TY + 8 rows of 36 nx bytes from one base with
-// 32-bit offsets, which bounds the width (about 3.7M nodes); wider lattices
-// take single steps too.
+// Two FP32 steps per launch (step2_kernel) on the largest of three tiles
+// that gives at least one tile per CU: 64 x 24, else 64 x 16, else 32 x 8.
+// On the small lattices of the last two a step lasts a few microseconds and
+// the launches set the pace, so half the launches outweigh the larger share
+// of recomputed ring nodes.  Measured, time per step against single steps:
+// 256^2 2.92 against 3.61 us (32 x 8; 64 x 16: 3.93), 512^2 4.14 against
+// 5.37 us (64 x 16; 32 x 8: 4.68); 32 x 16 and 64 x 8 were no faster.  The
+// tiles address TY + 8 rows of 36 nx bytes from one base with 32-bit
+// offsets, which bounds the width (about 3.7M nodes); wider lattices take
+// single steps.
 #ifndef LBM_FUSE_STEPS
 #define LBM_FUSE_STEPS 1
 #endif
-bool use_step2(const lbm_ctx* ctx) {
-  const unsigned long long band = 36ull * (unsigned long long)ctx->p.nx * (Step2Tile::TY + 8);
-  return LBM_FUSE_STEPS && ctx->p.storage == LBM_FP32 && band < (1ull << 32) &&
-         tiles_total<Step2Tile>(ctx->p.nx, ctx->p.ny) >= ctx->cus;
+using Step2Mid = Tile2Shape<64, 16, 8>;
+using Step2Small = Tile2Shape<32, 8, 8>;
+static_assert(Step2Mid::TY <= Step2Tile::TY && Step2Small::TY <= Step2Tile::TY,
+              "the width bound of the large tile covers the others");
+
+// 0: single steps; 1, 2, 3: two steps on Step2Tile, Step2Mid, Step2Small.
+int step2_shape(const lbm_ctx* ctx) {
+  const int nx = ctx->p.nx, ny = ctx->p.ny;
+  const unsigned long long band = 36ull * (unsigned long long)nx * (Step2Tile::TY + 8);
+  if (!LBM_FUSE_STEPS || ctx->p.storage != LBM_FP32 || band >= (1ull << 32)) return 0;
+  if (tiles_total<Step2Tile>(nx, ny) >= ctx->cus) return 1;
+  return tiles_total<Step2Mid>(nx, ny) >= ctx->cus ? 2 : 3;
 }
+bool use_step2(const lbm_ctx* ctx) { return step2_shape(ctx) != 0; }
 
 // src (time t) -> dst (time t + 2), and mid (time t + 1) if kMid.
-template <bool kMid>
-void launch_step2(const lbm_ctx* ctx, const void* src, void* mid, void* dst) {
-  using S = Step2Tile;
+template <class S, bool kMid>
+void launch_step2_on(const lbm_ctx* ctx, const void* src, void* mid, void* dst) {
   const int nx = ctx->p.nx, ny = ctx->p.ny, ntx = tiles_x<S>(nx), nt = tiles_total<S>(nx, ny);
   step2_kernel<S, kMid><<<nt, dim3(S::TX, S::WY), 0, ctx->stream>>>(
       static_cast<const float*>(src), static_cast<float*>(mid), static_cast<float*>(dst), nx, ny, ntx, nt,
       strip_width(nx, S::TX, false), ctx->c);
+}
+template <bool kMid>
+void launch_step2(const lbm_ctx* ctx, const void* src, void* mid, void* dst) {
+  switch (step2_shape(ctx)) {
+    case 1: launch_step2_on<Step2Tile, kMid>(ctx, src, mid, dst); break;
+    case 2: launch_step2_on<Step2Mid, kMid>(ctx, src, mid, dst); break;
+    default: launch_step2_on<Step2Small, kMid>(ctx, src, mid, dst); break;
+  }
 }
 
 int check_ctx(const lbm_ctx* ctx, bool need_state) {
@@ -1488,7 +1509,9 @@ int set_device(const lbm_ctx* ctx) {
   return LBM_OK;
 }
 
-size_t grid1(size_t n) { return (n + BLK - 1) / BLK; }
+// Workgroups of one node per thread; lbm_create admits 9 nx ny < 2^31, so
+// the count fits a grid dimension.
+unsigned grid1(size_t n) { return static_cast<unsigned>((n + BLK - 1) / BLK); }
 
 // Call fn with the storage policy of the context.
 template <class Fn>

@@ -146,14 +146,18 @@ def test_moments_fields_and_totals():
 
 @pytest.mark.parametrize("nx,ny,n", [(4096, 1024, 6), (1000, 700, 5), (2048 + 37, 1024 + 11, 7),
                                      (16384, 8192, 2), (16384, 1, 3), (20000, 9, 4), (7, 60000, 4),
-                                     (70, 9000, 3)])
+                                     (70, 9000, 3), (512, 512, 5), (600, 583, 4), (256, 256, 7),
+                                     (300, 200, 6), (37, 29, 5), (5, 200, 3), (64, 1, 4), (3, 2, 5),
+                                     (1, 1, 4)])
 def test_two_step_launches_match_single_steps(nx, ny, n):
-    """lbm_step(n) on lattices with at least one 64 x 24 tile per CU runs
-    two steps per launch (interior tiles with 32-bit offsets, edge tiles
+    """lbm_step(n) on FP32 lattices runs two steps per launch on 64 x 24
+    tiles (from 4096 x 1024 to 70 x 9000), on 64 x 16 tiles where those
+    give fewer tiles than CUs (512^2, 600 x 583) and on 32 x 8 tiles below
+    (256^2 down to 1 x 1): interior tiles with 32-bit offsets, edge tiles
     with wrapped 64-bit addresses, ragged tiles, an odd remainder as one
     single step, a state above 4 GiB, and lattices thinner than the loaded
-    region, down to one row or seven columns, where it wraps more than
-    once): bitwise the result of n calls of lbm_step(1)."""
+    region, down to one node, where it wraps more than once: bitwise the
+    result of n calls of lbm_step(1)."""
     _, co = params_pair(nx, ny, tr=0.7, width=10.0)
     rng = np.random.default_rng(nx + ny)
     rho = wl._f32(0.5 * (co.rho_g + co.rho_l) + rng.uniform(-0.01, 0.01, (ny, nx)))
@@ -166,13 +170,16 @@ def test_two_step_launches_match_single_steps(nx, ny, n):
     assert b.time == n and torch.equal(b.state(), fa)
 
 
-def test_two_step_chain_matches_single_steps():
+@pytest.mark.parametrize("nx,ny", [(1000, 700), (512, 512), (300, 200)])
+def test_two_step_chain_matches_single_steps(nx, ny):
     """lbm_step_saved_chain over distinct buffers (two steps per launch,
-    the state between them written too) and over alternating buffers (one
-    step per launch): bitwise lbm_step_saved, step by step."""
-    nx, ny, n = 1000, 700, 5
+    the state between them written too; 64 x 24, 64 x 16 and 32 x 8 tiles)
+    and over alternating buffers (one step per launch): bitwise
+    lbm_step_saved, step by step."""
+    n = 5
     _, co = params_pair(nx, ny, tr=0.7, width=10.0)
-    rho = wl.droplets(nx, ny, co.rho_g, co.rho_l, co.width, [(400, 300), (650, 420)], [120.0, 90.0])
+    rho = wl.droplets(nx, ny, co.rho_g, co.rho_l, co.width, [(0.4 * nx, 0.43 * ny), (0.65 * nx, 0.6 * ny)],
+                      [0.17 * min(nx, ny), 0.13 * min(nx, ny)])
     lat = lattice(nx, ny, rho, tr=0.7, width=10.0)
     single = [lat.save_state()] + [lat.checkpoint_buffer() for _ in range(n)]
     for j in range(n):
