@@ -51,12 +51,15 @@ def test_set_get_state_roundtrip_is_exact():
                                          (1300, 410, 10), (1024, 256, 10), (1024, 512, 6)])
 def test_step_parity_ragged(nx, ny, steps):
     """Several tiles and a ragged tail in both directions; 772 x 37 also has
-    interior tiles (the fast addressing path) next to edge tiles.  Lattices
-    with fewer 256 x 8 tiles than CUs run smaller tiles; 1300 x 410 (312
-    tiles) runs the 256 x 8 tiles of the large workloads, with ragged tails.
-    Widths that are multiples of 64 address the FP32 state relative to the
-    tile's run: 1024 x 256 with the 128 x 8 tiles, 1024 x 512 with the
-    256 x 8 tiles (256 of them)."""
+    interior tiles (the fast addressing path) next to edge tiles.  The first
+    chunk of one step runs the one-step kernel: lattices with fewer 256 x 8
+    tiles than CUs run smaller tiles; 1300 x 410 (312 tiles) runs the
+    256 x 8 tiles of the large workloads, with ragged tails; widths that
+    are multiples of 64 address the FP32 state relative to the tile's run:
+    1024 x 256 with the 128 x 8 tiles, 1024 x 512 with the 256 x 8 tiles
+    (256 of them).  The rest runs two steps per launch (64 x 24 tiles on
+    1300 x 410 and 1024 x 512, 64 x 16 on 1024 x 256, 32 x 8 on the
+    others) and one for an odd remainder."""
     co, rho, ux, uy = droplet_case(nx, ny, seed=nx)
     lat = lattice(nx, ny, rho, ux, uy, tr=0.8)
     f = oracle_init(co, rho, ux, uy)
@@ -88,7 +91,8 @@ def test_step_parity_sheared_droplet():
 @pytest.mark.parametrize("nx,ny", [(1, 1), (1, 64), (3, 2), (2, 5), (64, 1)])
 def test_step_parity_degenerate(nx, ny):
     """Lattices narrower than the stencil: periodic images of a node are its
-    own neighbours."""
+    own neighbours.  One step (the one-step kernel), then 19 (two steps per
+    launch on 32 x 8 tiles, and one)."""
     _, co = params_pair(nx, ny, tr=0.7)
     rng = np.random.default_rng(nx * 100 + ny)
     if nx == 1 and ny == 64:
@@ -97,8 +101,10 @@ def test_step_parity_degenerate(nx, ny):
         rho = wl._f32(rng.uniform(0.15, 0.21, (ny, nx)))
     lat = lattice(nx, ny, rho, tr=0.7)
     f = oracle_init(co, rho)
-    lat.step(20)
-    compare(lat, lbm.run(f, co, 20), co)
+    for chunk in (1, 19):
+        lat.step(chunk)
+        f = lbm.run(f, co, chunk)
+        compare(lat, f, co)
 
 
 def test_uniform_state_is_fixed_point():
