@@ -213,9 +213,9 @@ NONDEFAULT = dict(s_p=0.8, s_eps=1.4, varpi=0.12, a=0.5, b=2.5, r_gas=1.5, tr=0.
 
 @pytest.mark.parametrize("nx,ny", [(200, 70), (1024, 384)])
 def test_step_parity_nondefault_parameters(nx, ny):
-    """Parity at NONDEFAULT on a lattice run one step per launch (200 x 70)
-    and on one run two steps per launch (1024 x 384: one 64 x 24 tile per
-    CU), after 1 and after 6 steps."""
+    """Parity at NONDEFAULT after one step (the one-step kernel) and after
+    five more (two steps per launch, then one) on 200 x 70 (32 x 8 tiles)
+    and 1024 x 384 (64 x 24 tiles, one per CU)."""
     _, co = params_pair(nx, ny, **NONDEFAULT)
     rho = wl.droplets(nx, ny, co.rho_g, co.rho_l, co.width, [(nx * 0.45, ny * 0.55)], [min(nx, ny) * 0.3])
     rng = np.random.default_rng(nx)
